@@ -1,0 +1,144 @@
+"""CPU oracle for the S-box Walsh spectrum / nonlinearity path.
+
+TEST INFRASTRUCTURE ONLY: the test-suite, the smoke check and the
+benchmark's CPU-baseline leg are the only callers.  The product path (the
+HIP library and its Python binding) never imports this package, and the two
+share no code.  The arithmetic lives in ``walsh_oracle.c`` (plain C, built
+with gcc); this module only builds it, loads it and marshals numpy arrays.
+
+Every routine follows the paper's definitions: the Walsh matrix of Eq. 1
+(exponent read as <a,x> xor <b,S(x)>), the component functions of Eq. 2,
+the nonlinearity of Eq. 3 over the nonzero output masks, the column-wise
+fast transform of Algorithm 1, the fused per-column maximum of
+Algorithm 3 and the minimum of Algorithm 6.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "walsh_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+B_MAJOR = 1
+A_MAJOR = 2
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, OpenMP over masks).  Returns the .so path."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-std=c11", "-Wall", "-Wextra",
+               "-o", tmp, _SRC]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        lib = ctypes.CDLL(_LIB)
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        u32p = ctypes.POINTER(ctypes.c_uint32)
+        lib.oracle_walsh_nl.argtypes = [u32p, ctypes.c_int, ctypes.c_int, i32p, i32p, ctypes.c_int]
+        lib.oracle_walsh_maxabs_masks.argtypes = [u32p, ctypes.c_int, ctypes.c_int, u32p,
+                                                  ctypes.c_int64, i32p, ctypes.c_int]
+        lib.oracle_spectrum.argtypes = [u32p, ctypes.c_int, ctypes.c_int, ctypes.c_int, i32p]
+        lib.oracle_nl_from_spectrum.argtypes = [i32p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                                i32p, i32p]
+        lib.oracle_walsh_column.argtypes = [u32p, ctypes.c_int, ctypes.c_int, ctypes.c_uint32, i32p]
+        lib.oracle_walsh_entry.argtypes = [u32p, ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32]
+        lib.oracle_walsh_entry.restype = ctypes.c_int32
+        for f in (lib.oracle_walsh_nl, lib.oracle_walsh_maxabs_masks, lib.oracle_spectrum,
+                  lib.oracle_nl_from_spectrum, lib.oracle_walsh_column):
+            f.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _table(S, n: int) -> np.ndarray:
+    t = np.ascontiguousarray(np.asarray(S).astype(np.uint32, copy=False).reshape(-1))
+    if t.size != (1 << n):
+        raise ValueError("S must have 2^n = %d entries, got %d" % (1 << n, t.size))
+    return t
+
+
+def _p(a, ct):
+    return a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+def walsh_nl(S, n: int, m: int, nthreads: int = 1):
+    """Fused per-mask transform + maximum.  Returns (nl, maxabs[2^m] int32)."""
+    lib = _load()
+    t = _table(S, n)
+    maxabs = np.empty(1 << m, dtype=np.int32)
+    nl = np.zeros(1, dtype=np.int32)
+    rc = lib.oracle_walsh_nl(_p(t, ctypes.c_uint32), n, m, _p(maxabs, ctypes.c_int32),
+                             _p(nl, ctypes.c_int32), int(nthreads))
+    if rc != 0:
+        raise ValueError("oracle_walsh_nl rejected its arguments")
+    return int(nl[0]), maxabs
+
+
+def maxabs_for_masks(S, n: int, m: int, masks, nthreads: int = 1) -> np.ndarray:
+    """max_a |W(a, b)| for each listed nonzero mask b."""
+    lib = _load()
+    t = _table(S, n)
+    bs = np.ascontiguousarray(np.asarray(masks, dtype=np.uint32).reshape(-1))
+    out = np.empty(bs.size, dtype=np.int32)
+    rc = lib.oracle_walsh_maxabs_masks(_p(t, ctypes.c_uint32), n, m, _p(bs, ctypes.c_uint32),
+                                       bs.size, _p(out, ctypes.c_int32), int(nthreads))
+    if rc != 0:
+        raise ValueError("oracle_walsh_maxabs_masks rejected its arguments")
+    return out
+
+
+def spectrum(S, n: int, m: int, layout: int = B_MAJOR) -> np.ndarray:
+    """Full spectrum, shape (2^m, 2^n) for B_MAJOR or (2^n, 2^m) for A_MAJOR."""
+    lib = _load()
+    t = _table(S, n)
+    W = np.empty(1 << (n + m), dtype=np.int32)
+    rc = lib.oracle_spectrum(_p(t, ctypes.c_uint32), n, m, int(layout), _p(W, ctypes.c_int32))
+    if rc != 0:
+        raise ValueError("oracle_spectrum rejected its arguments")
+    return W.reshape((1 << m, 1 << n) if layout == B_MAJOR else (1 << n, 1 << m))
+
+
+def nl_from_spectrum(W, n: int, m: int, layout: int = B_MAJOR):
+    """Unfused re-scan of a stored spectrum.  Returns (nl, maxabs[2^m])."""
+    lib = _load()
+    w = np.ascontiguousarray(np.asarray(W, dtype=np.int32).reshape(-1))
+    maxabs = np.empty(1 << m, dtype=np.int32)
+    nl = np.zeros(1, dtype=np.int32)
+    rc = lib.oracle_nl_from_spectrum(_p(w, ctypes.c_int32), n, m, int(layout),
+                                     _p(maxabs, ctypes.c_int32), _p(nl, ctypes.c_int32))
+    if rc != 0:
+        raise ValueError("oracle_nl_from_spectrum rejected its arguments")
+    return int(nl[0]), maxabs
+
+
+def walsh_column(S, n: int, m: int, b: int) -> np.ndarray:
+    """W(a, b) for all a."""
+    lib = _load()
+    t = _table(S, n)
+    col = np.empty(1 << n, dtype=np.int32)
+    rc = lib.oracle_walsh_column(_p(t, ctypes.c_uint32), n, m, int(b), _p(col, ctypes.c_int32))
+    if rc != 0:
+        raise ValueError("oracle_walsh_column rejected its arguments")
+    return col
+
+
+def walsh_entry(S, n: int, a: int, b: int) -> int:
+    """W(a, b) summed straight from the definition."""
+    lib = _load()
+    t = _table(S, n)
+    return int(lib.oracle_walsh_entry(_p(t, ctypes.c_uint32), n, int(a), int(b)))

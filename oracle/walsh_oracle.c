@@ -1,0 +1,225 @@
+/*
+ * walsh_oracle.c -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, obviously correct CPU implementation of what the S-box
+ * Walsh-spectrum / nonlinearity path computes.  Only the test-suite, the
+ * smoke check and the benchmark's CPU-baseline leg may load this library;
+ * the product path (the HIP library) never links, calls or imports it, and
+ * this file shares no code with it.
+ *
+ * Conventions (the readings of the paper that every routine below follows):
+ *   - An n x m S-box is a table S[0 .. 2^n) of values < 2^m (bits at or
+ *     above m are ignored).  Component function for output mask b is
+ *     x -> parity(b & S[x])  (Section 3, Eq. 2: a linear combination of the
+ *     coordinate functions f_i = bit i of S(x)).
+ *   - Walsh spectrum (Section 3, Eq. 1, exponent read as <u,x> + <v,S(x)>):
+ *        W(a, b) = sum_x (-1)^( parity(a & x) XOR parity(b & S[x]) ),
+ *     for a in [0, 2^n), b in [0, 2^m).
+ *   - Nonlinearity (Section 3, Eq. 3, with the all-zero output mask left
+ *     out, as in Algorithms 1-3 which only carry the 2^m - 1 nonzero
+ *     columns):
+ *        NL = 2^(n-1) - (1/2) max_{b != 0, a} |W(a, b)|.
+ *     Every W is congruent to 2^n mod 2, so the halving is exact.
+ *   - Polarity truth table sign: bit 0 -> +1, bit 1 -> -1.
+ *   - Fast transform (Algorithm 1 / Algorithm 3): radix-2 butterflies on
+ *     index pairs (i, i + h) with (i & h) == 0, h = 1, 2, 4, ..., in natural
+ *     (Sylvester) order, so output index == a.
+ *   - Per-mask maximum |W| and per-mask nl value (the "var" array of
+ *     Algorithms 2, 3 and 5), then the minimum over masks (Algorithm 6),
+ *     starting from 2^(n-1) rather than the paper's fixed sentinel.
+ *
+ * Layouts of a stored spectrum:
+ *   ORACLE_B_MAJOR (1): W[b * 2^n + a]  (the transposed matrix of Section 5.1)
+ *   ORACLE_A_MAJOR (2): W[a * 2^m + b]  (the matrix of Algorithm 1)
+ *
+ * Every entry point returns 0 on success and -1 on an invalid argument.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORACLE_B_MAJOR 1
+#define ORACLE_A_MAJOR 2
+
+/* parity of the set bits of v, by clearing the lowest set bit until none is left */
+static int parity32(uint32_t v) {
+    int p = 0;
+    while (v) {
+        v &= v - 1u;
+        p ^= 1;
+    }
+    return p;
+}
+
+static int valid_nm(int n, int m) {
+    return n >= 1 && n <= 24 && m >= 1 && m <= 24;
+}
+
+/* Component function of mask b as a polarity column: f[x] = (-1)^parity(b & S[x]). */
+static void polarity_column(const uint32_t* S, int n, uint32_t b, int32_t* f) {
+    const uint32_t N = 1u << n;
+    for (uint32_t x = 0; x < N; ++x) f[x] = parity32(b & S[x]) ? -1 : 1;
+}
+
+/* In-place fast Walsh-Hadamard transform of length 2^n (Algorithm 1 on one column). */
+static void fwht_inplace(int32_t* f, int n) {
+    const uint32_t N = 1u << n;
+    for (uint32_t h = 1; h < N; h <<= 1) {
+        for (uint32_t i = 0; i < N; i += 2 * h) {
+            for (uint32_t j = i; j < i + h; ++j) {
+                const int32_t u = f[j];
+                const int32_t v = f[j + h];
+                f[j] = u + v;
+                f[j + h] = u - v;
+            }
+        }
+    }
+}
+
+static int32_t max_abs(const int32_t* f, uint32_t N) {
+    int32_t best = 0;
+    for (uint32_t i = 0; i < N; ++i) {
+        const int32_t a = f[i] < 0 ? -f[i] : f[i];
+        if (a > best) best = a;
+    }
+    return best;
+}
+
+/*
+ * One Walsh column: col[a] = W(a, b) for a in [0, 2^n).  Any b (also 0).
+ */
+int oracle_walsh_column(const uint32_t* S, int n, int m, uint32_t b, int32_t* col) {
+    if (!S || !col || !valid_nm(n, m) || (m < 32 && b >= (1u << m))) return -1;
+    polarity_column(S, n, b, col);
+    fwht_inplace(col, n);
+    return 0;
+}
+
+/*
+ * One coefficient straight from the definition (Eq. 1), O(2^n).
+ */
+int32_t oracle_walsh_entry(const uint32_t* S, int n, uint32_t a, uint32_t b) {
+    const uint32_t N = 1u << n;
+    int32_t sum = 0;
+    for (uint32_t x = 0; x < N; ++x) sum += (parity32(a & x) ^ parity32(b & S[x])) ? -1 : 1;
+    return sum;
+}
+
+/*
+ * Fused path (Algorithm 3 + Algorithm 6): for every nonzero mask b,
+ * transform its column, keep only max_a |W(a,b)|; then NL is the minimum
+ * of (2^n - max) / 2 over b.  maxabs (2^m entries, may be NULL) receives
+ * the per-mask maximum, with maxabs[0] = 2^n (row b = 0 is 2^n at a = 0).
+ * nthreads <= 1 runs serially; larger values split the masks into
+ * contiguous blocks, one per OpenMP thread (the split of Algorithm 5).
+ */
+int oracle_walsh_nl(const uint32_t* S, int n, int m, int32_t* maxabs, int32_t* nl, int nthreads) {
+    if (!S || !nl || !valid_nm(n, m)) return -1;
+    const uint32_t N = 1u << n;
+    const int64_t M = (int64_t)1 << m;
+    int32_t best = (int32_t)(N >> 1);
+    int failed = 0;
+    if (maxabs) maxabs[0] = (int32_t)N;
+    if (nthreads < 1) nthreads = 1;
+#pragma omp parallel num_threads(nthreads) reduction(min : best) reduction(| : failed)
+    {
+        int32_t* f = (int32_t*)malloc(sizeof(int32_t) * N);
+        if (!f) {
+            failed = 1;
+        } else {
+#pragma omp for schedule(static)
+            for (int64_t b = 1; b < M; ++b) {
+                polarity_column(S, n, (uint32_t)b, f);
+                fwht_inplace(f, n);
+                const int32_t mx = max_abs(f, N);
+                if (maxabs) maxabs[b] = mx;
+                const int32_t nlb = ((int32_t)N - mx) >> 1;
+                if (nlb < best) best = nlb;
+            }
+            free(f);
+        }
+    }
+    if (failed) return -1;
+    *nl = best;
+    return 0;
+}
+
+/*
+ * Same fused path restricted to the masks listed in bs[0..count) (all
+ * nonzero); maxabs_out[i] receives max_a |W(a, bs[i])|.  Used to time or
+ * check a bounded sample of a large S-box.
+ */
+int oracle_walsh_maxabs_masks(const uint32_t* S, int n, int m, const uint32_t* bs, int64_t count,
+                              int32_t* maxabs_out, int nthreads) {
+    if (!S || !bs || !maxabs_out || !valid_nm(n, m) || count < 0) return -1;
+    const uint32_t N = 1u << n;
+    int failed = 0;
+    if (nthreads < 1) nthreads = 1;
+#pragma omp parallel num_threads(nthreads) reduction(| : failed)
+    {
+        int32_t* f = (int32_t*)malloc(sizeof(int32_t) * N);
+        if (!f) {
+            failed = 1;
+        } else {
+#pragma omp for schedule(static)
+            for (int64_t i = 0; i < count; ++i) {
+                polarity_column(S, n, bs[i], f);
+                fwht_inplace(f, n);
+                maxabs_out[i] = max_abs(f, N);
+            }
+            free(f);
+        }
+    }
+    return failed ? -1 : 0;
+}
+
+/*
+ * Full spectrum (all 2^(n+m) coefficients, row b = 0 included) in the
+ * requested layout.  W must hold 2^(n+m) int32.
+ */
+int oracle_spectrum(const uint32_t* S, int n, int m, int layout, int32_t* W) {
+    if (!S || !W || !valid_nm(n, m) || n + m > 30) return -1;
+    if (layout != ORACLE_B_MAJOR && layout != ORACLE_A_MAJOR) return -1;
+    const uint32_t N = 1u << n;
+    const uint32_t M = 1u << m;
+    int32_t* f = (int32_t*)malloc(sizeof(int32_t) * N);
+    if (!f) return -1;
+    for (uint32_t b = 0; b < M; ++b) {
+        polarity_column(S, n, b, f);
+        fwht_inplace(f, n);
+        for (uint32_t a = 0; a < N; ++a) {
+            if (layout == ORACLE_B_MAJOR)
+                W[(size_t)b * N + a] = f[a];
+            else
+                W[(size_t)a * M + b] = f[a];
+        }
+    }
+    free(f);
+    return 0;
+}
+
+/*
+ * Unfused path (Algorithm 2, then Algorithm 6): re-scan a stored spectrum
+ * for the per-mask maximum and the nonlinearity.  maxabs may be NULL.
+ */
+int oracle_nl_from_spectrum(const int32_t* W, int n, int m, int layout, int32_t* maxabs, int32_t* nl) {
+    if (!W || !nl || !valid_nm(n, m) || n + m > 30) return -1;
+    if (layout != ORACLE_B_MAJOR && layout != ORACLE_A_MAJOR) return -1;
+    const uint32_t N = 1u << n;
+    const uint32_t M = 1u << m;
+    int32_t best = (int32_t)(N >> 1);
+    for (uint32_t b = 0; b < M; ++b) {
+        int32_t mx = 0;
+        for (uint32_t a = 0; a < N; ++a) {
+            const int32_t w = layout == ORACLE_B_MAJOR ? W[(size_t)b * N + a] : W[(size_t)a * M + b];
+            const int32_t aw = w < 0 ? -w : w;
+            if (aw > mx) mx = aw;
+        }
+        if (maxabs) maxabs[b] = mx;
+        if (b == 0) continue;
+        const int32_t nlb = ((int32_t)N - mx) >> 1;
+        if (nlb < best) best = nlb;
+    }
+    *nl = best;
+    return 0;
+}

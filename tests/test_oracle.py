@@ -1,0 +1,242 @@
+"""Pins for the CPU oracle: each check comes from the definition, a library
+routine, an identity of the Walsh transform or a closed form -- never from
+the oracle itself.  A plausible mistake (a dropped term, a wrong sign, a
+transposed operand, a wrong bit order) fails at least one of them."""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+import oracle
+from paper_1912_03732_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- helpers ---
+
+def popcount(v):
+    return np.bitwise_count(np.asarray(v, dtype=np.uint64)).astype(np.int64)
+
+
+def brute_spectrum_amajor(S, n, m):
+    """Eq. 1 written out: W[a, b] = sum_x (-1)^(a.x + b.S(x)) as a product of
+    two +-1 matrices (the characters of x and of S(x))."""
+    x = np.arange(1 << n)
+    a = np.arange(1 << n)
+    b = np.arange(1 << m)
+    chi_ax = 1 - 2 * (popcount(a[:, None] & x[None, :]) & 1)          # [a, x]
+    chi_bs = 1 - 2 * (popcount(np.asarray(S, dtype=np.int64)[:, None] & b[None, :]) & 1)  # [x, b]
+    return chi_ax @ chi_bs
+
+
+def pure_python_entry(S, n, a, b):
+    total = 0
+    for x in range(1 << n):
+        e = bin(a & x).count("1") + bin(b & int(S[x])).count("1")
+        total += -1 if e % 2 else 1
+    return total
+
+
+def random_invertible(k, g):
+    while True:
+        M = g.integers(0, 2, size=(k, k), dtype=np.int64)
+        # rank over GF(2) by elimination
+        A = M.copy()
+        r = 0
+        for c in range(k):
+            piv = [i for i in range(r, k) if A[i, c]]
+            if not piv:
+                continue
+            A[[r, piv[0]]] = A[[piv[0], r]]
+            for i in range(k):
+                if i != r and A[i, c]:
+                    A[i] ^= A[r]
+            r += 1
+        if r == k:
+            return M
+
+
+def apply_linear(M, v):
+    """y = M v over GF(2), v given as integers (bit j = coordinate j)."""
+    v = np.asarray(v, dtype=np.int64)
+    k = M.shape[0]
+    bits = (v[:, None] >> np.arange(k)[None, :]) & 1            # [N, k]
+    ybits = (bits @ M.T) & 1                                      # [N, k]
+    return (ybits << np.arange(k)[None, :]).sum(axis=1)
+
+
+# ------------------------------------------------------------------ pins ---
+
+@pytest.mark.parametrize("n,m", [(1, 1), (1, 3), (2, 2), (3, 1), (3, 5), (4, 4), (5, 2), (5, 6),
+                                 (6, 6), (7, 3), (8, 8), (6, 9)])
+def test_spectrum_equals_definition(n, m):
+    S = inputs.random_function(n, m, inputs.rng(100 + 10 * n + m))
+    ref = brute_spectrum_amajor(S, n, m)
+    got_a = oracle.spectrum(S, n, m, oracle.A_MAJOR)
+    got_b = oracle.spectrum(S, n, m, oracle.B_MAJOR)
+    assert np.array_equal(got_a, ref)
+    assert np.array_equal(got_b, ref.T)
+
+
+def test_pure_python_definition_tiny():
+    S = inputs.permutation(4, inputs.rng(11))
+    W = oracle.spectrum(S, 4, 4, oracle.A_MAJOR)
+    for a in range(16):
+        for b in range(16):
+            assert W[a, b] == pure_python_entry(S, 4, a, b)
+
+
+@pytest.mark.parametrize("n", [4, 7, 10, 12])
+def test_columns_equal_sylvester_hadamard_product(n):
+    """Library pin: scipy's Sylvester Hadamard matrix times the polarity truth table."""
+    m = min(n, 10)
+    g = inputs.rng(200 + n)
+    S = inputs.random_function(n, m, g)
+    H = scipy.linalg.hadamard(1 << n).astype(np.float64)
+    masks = np.arange(1 << m) if m <= 6 else g.choice(1 << m, size=48, replace=False)
+    ptt = 1 - 2 * (popcount(np.asarray(S, dtype=np.int64)[:, None] & masks[None, :]) & 1)
+    ref = np.rint(H @ ptt.astype(np.float64)).astype(np.int64)
+    for k, b in enumerate(masks):
+        assert np.array_equal(oracle.walsh_column(S, n, m, int(b)), ref[:, k])
+
+
+def test_entry_from_definition_matches_columns():
+    S = inputs.random_function(11, 9, inputs.rng(5))
+    g = inputs.rng(6)
+    for _ in range(20):
+        a = int(g.integers(0, 1 << 11))
+        b = int(g.integers(0, 1 << 9))
+        assert oracle.walsh_entry(S, 11, a, b) == oracle.walsh_column(S, 11, 9, b)[a]
+
+
+@pytest.mark.parametrize("n,m", [(5, 5), (8, 8), (9, 4), (6, 11)])
+def test_walsh_identities(n, m):
+    S = inputs.random_function(n, m, inputs.rng(300 + n * m))
+    W = oracle.spectrum(S, n, m, oracle.B_MAJOR).astype(np.int64)   # [b, a]
+    # Parseval for every column
+    assert np.all((W * W).sum(axis=1) == 1 << (2 * n))
+    # sum over a gives 2^n times the sign of the component at x = 0
+    sgn = 1 - 2 * (popcount(np.arange(1 << m) & int(S[0])) & 1)
+    assert np.array_equal(W.sum(axis=1), (1 << n) * sgn)
+    # row b = 0 is 2^n at a = 0 and 0 elsewhere
+    assert W[0, 0] == 1 << n and np.all(W[0, 1:] == 0)
+    # every coefficient is congruent to 2^n mod 2 (even for n >= 1)
+    assert np.all(W % 2 == 0)
+
+
+@pytest.mark.parametrize("n", [3, 6, 8, 9])
+def test_permutation_balanced_and_inverse_duality(n):
+    S = inputs.permutation(n, inputs.rng(400 + n)).astype(np.int64)
+    Sinv = np.empty_like(S)
+    Sinv[S] = np.arange(1 << n)
+    W = oracle.spectrum(S, n, n, oracle.A_MAJOR)
+    Winv = oracle.spectrum(Sinv, n, n, oracle.A_MAJOR)
+    # a permutation has balanced components: W(0, b) = 0 for b != 0
+    assert np.all(W[0, 1:] == 0)
+    # W_{S^-1}(a, b) = W_S(b, a)
+    assert np.array_equal(Winv, W.T)
+
+
+@pytest.mark.parametrize("n", [6, 8, 10, 12])
+def test_gf_inversion_closed_form(n):
+    """Nyberg: inversion in GF(2^n), n even, has NL = 2^(n-1) - 2^(n/2)."""
+    nl, maxabs = oracle.walsh_nl(inputs.gf_inversion(n), n, n, nthreads=os.cpu_count())
+    assert nl == (1 << (n - 1)) - (1 << (n // 2))
+    assert maxabs[0] == 1 << n
+
+
+@pytest.mark.slow
+def test_gf_inversion_16_closed_form():
+    nl, maxabs = oracle.walsh_nl(inputs.gf_inversion(16, 0x1002D), 16, 16, nthreads=os.cpu_count())
+    assert nl == 32768 - 256 == 32512
+    assert int(maxabs[1:].max()) == 512
+
+
+def test_paper_table2_aes_value():
+    with open(os.path.join(GOLDEN, "paper_table2.json")) as f:
+        gold = json.load(f)
+    nl, _ = oracle.walsh_nl(inputs.aes_sbox(), 8, 8)
+    assert nl == gold["aes_8x8_nl"]
+    # the fused (Algorithm 3/6) and unfused (Algorithm 1 then 2) routes agree, as in Table 2
+    W = oracle.spectrum(inputs.aes_sbox(), 8, 8, oracle.B_MAJOR)
+    assert oracle.nl_from_spectrum(W, 8, 8, oracle.B_MAJOR)[0] == gold["aes_8x8_nl"]
+
+
+@pytest.mark.parametrize("n,m", [(4, 4), (7, 5), (9, 9), (10, 3), (5, 12)])
+def test_fused_equals_unfused(n, m):
+    S = inputs.random_function(n, m, inputs.rng(500 + n + m))
+    nl, maxabs = oracle.walsh_nl(S, n, m)
+    for layout in (oracle.B_MAJOR, oracle.A_MAJOR):
+        W = oracle.spectrum(S, n, m, layout)
+        nl2, maxabs2 = oracle.nl_from_spectrum(W, n, m, layout)
+        assert nl == nl2 and np.array_equal(maxabs, maxabs2)
+    # and the per-mask maximum equals the brute-force definition
+    ref = np.abs(brute_spectrum_amajor(S, n, m)).max(axis=0) if n + m <= 16 else None
+    if ref is not None:
+        assert np.array_equal(maxabs, ref)
+
+
+def test_threaded_equals_serial():
+    S = inputs.random_function(11, 10, inputs.rng(9))
+    assert oracle.walsh_nl(S, 11, 10, nthreads=1)[0] == oracle.walsh_nl(S, 11, 10, nthreads=4)[0]
+    assert np.array_equal(oracle.walsh_nl(S, 11, 10, nthreads=1)[1], oracle.walsh_nl(S, 11, 10, nthreads=4)[1])
+    masks = np.array([1, 7, 1023, 512, 3])
+    assert np.array_equal(oracle.maxabs_for_masks(S, 11, 10, masks, nthreads=3),
+                          oracle.walsh_nl(S, 11, 10)[1][masks])
+
+
+@pytest.mark.parametrize("n,m", [(5, 5), (8, 6), (9, 9)])
+def test_affine_box_has_zero_nonlinearity(n, m):
+    g = inputs.rng(600 + n)
+    M = g.integers(0, 2, size=(m, n), dtype=np.int64)
+    c = int(g.integers(0, 1 << m))
+    x = np.arange(1 << n)
+    bits = (x[:, None] >> np.arange(n)[None, :]) & 1
+    S = ((bits @ M.T) & 1) @ (1 << np.arange(m)) ^ c
+    nl, _ = oracle.walsh_nl(S, n, m)
+    assert nl == 0
+
+
+@pytest.mark.parametrize("n", [6, 8, 10])
+def test_bent_function_closed_form(n):
+    """m = 1: f(x) = <x_lo, x_hi> (Maiorana-McFarland) is bent, NL = 2^(n-1) - 2^(n/2-1),
+    and |W(a, 1)| = 2^(n/2) for every a."""
+    h = n // 2
+    x = np.arange(1 << n)
+    S = popcount((x & ((1 << h) - 1)) & (x >> h)) & 1
+    nl, maxabs = oracle.walsh_nl(S, n, 1)
+    assert nl == (1 << (n - 1)) - (1 << (h - 1))
+    col = oracle.walsh_column(S, n, 1, 1)
+    assert np.all(np.abs(col) == 1 << h)
+
+
+@pytest.mark.parametrize("n,m", [(6, 6), (8, 8), (7, 9)])
+def test_affine_equivalence_invariance(n, m):
+    g = inputs.rng(700 + n + m)
+    S = inputs.random_function(n, m, g).astype(np.int64)
+    A = random_invertible(m, g)
+    B = random_invertible(n, g)
+    c = int(g.integers(0, 1 << m))
+    d = int(g.integers(0, 1 << n))
+    x = np.arange(1 << n)
+    S2 = apply_linear(A, S[apply_linear(B, x) ^ d]) ^ c
+    assert oracle.walsh_nl(S, n, m)[0] == oracle.walsh_nl(S2, n, m)[0]
+    # the multiset of per-mask maxima is also preserved (masks are permuted by A^T)
+    assert sorted(oracle.walsh_nl(S, n, m)[1].tolist()) == sorted(oracle.walsh_nl(S2, n, m)[1].tolist())
+
+
+def test_high_table_bits_are_ignored():
+    S = inputs.random_function(7, 5, inputs.rng(12)).astype(np.uint32)
+    junk = S | (inputs.random_function(7, 8, inputs.rng(13)).astype(np.uint32) << 5)
+    assert oracle.walsh_nl(S, 7, 5)[0] == oracle.walsh_nl(junk, 7, 5)[0]
+    assert np.array_equal(oracle.walsh_nl(S, 7, 5)[1], oracle.walsh_nl(junk, 7, 5)[1])
+
+
+def test_invalid_arguments_rejected():
+    with pytest.raises(ValueError):
+        oracle.walsh_nl(np.zeros(8, np.uint8), 4, 4)       # wrong table size
+    with pytest.raises(ValueError):
+        oracle.walsh_nl(np.zeros(2, np.uint8), 1, 0)       # m = 0
