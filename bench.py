@@ -1,0 +1,194 @@
+"""Benchmark: fused Walsh spectrum + nonlinearity of a 16x16 S-box on one MI355X.
+
+One step = one pass of the whole path over the 16x16 random-permutation
+S-box (65,535 nonzero output masks x a 65,536-point transform each, fused
+max |W| per mask and NL, no spectrum stored): bit-slicing of the table,
+initialisation, and the fused transform kernel.  The table, outputs and
+workspace are resident in HBM before timing starts.
+
+Prints one JSON line (rank 0, N = 1) with the throughput in Walsh
+coefficients per second, the roofline of the dominant kernel and the CPU
+oracle's rate on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 3.93e13 32-bit VALU lane-ops/s;
+# packed 16-bit ops (v_pk_add_u16 ...) do two element-ops per lane-op.
+PEAK_INT32_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+PEAK_PK16_TOPS = 2 * PEAK_INT32_TOPS
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-sample-masks", type=int, default=8192,
+                    help="masks of the 16x16 box the CPU oracle is timed on")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--batched", action="store_true", help="also time the mixed 4096-box batch")
+    return ap.parse_args()
+
+
+def host_cores() -> int:
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit():
+        n = min(n, int(env))
+    return max(1, n)
+
+
+def cpu_baseline(S, n, m, sample_masks):
+    import numpy as np
+    import oracle
+    cores = host_cores()
+    masks = np.arange(1, min(sample_masks, (1 << m) - 1) + 1, dtype=np.uint32)
+    oracle.maxabs_for_masks(S, n, m, masks[:64], nthreads=cores)  # load + warm
+    t0 = time.perf_counter()
+    oracle.maxabs_for_masks(S, n, m, masks, nthreads=cores)
+    dt = time.perf_counter() - t0
+    return {"value": masks.size * (1 << n) / dt, "unit": "coeff/s", "cores": cores, "kind": "oracle",
+            "sample": "masks b=1..%d of the same %dx%d box (%.1f s wall on %d threads)"
+                      % (masks.size, n, m, dt, cores)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the Walsh/NL path is built and timed on a single "
+              "MI355X (multi-GPU sharding over masks is a design note, not part of this build)",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_1912_03732_amd import binding as B
+    from paper_1912_03732_amd import inputs
+
+    n = m = 16
+    w = inputs.workload_16x16()
+    S_host = w["perm"]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    S = B.table_to_device(S_host, m, device=dev)
+    nl = torch.empty(1, dtype=torch.int32, device=dev)
+    mx = torch.empty(1 << m, dtype=torch.int32, device=dev)
+    ws = B.Workspace(B.sbox_walsh_nl_workspace_bytes(n, m, 0), dev)
+    stream = torch.cuda.current_stream(dev)
+    sptr = int(stream.cuda_stream)
+
+    def step():
+        st = B.sbox_walsh_nl_ex(S.data_ptr(), n, m, 2, mx.data_ptr(), nl.data_ptr(), 0, 0,
+                                ws.ptr, ws.nbytes, None, sptr)
+        if st != 0:
+            raise RuntimeError(B.last_error())
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize(dev)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record(stream)
+        step()
+        b.record(stream)
+    torch.cuda.synchronize(dev)
+    t1 = time.perf_counter()
+    nl_val = int(nl.item())
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    ev_ms = sorted(a.elapsed_time(b) for a, b in ev)
+    ev_mean = sum(ev_ms) / len(ev_ms)
+    coeffs = (1 << n) * ((1 << m) - 1)
+    ops = n * coeffs
+    value = coeffs / (ms_per_step * 1e-3)
+    achieved_tops = ops / (ev_mean * 1e-3) / 1e12
+
+    out = {
+        "metric": "Walsh coefficients/s, fused NL of a 16x16 S-box (65,535 masks x 65,536-point FWHT)",
+        "value": value,
+        "unit": "coeff/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "i16",
+        "data": "synthetic",
+        "config": {"workload": "single 16x16 S-box, seeded Fisher-Yates permutation (seed %d), fused "
+                               "max|W| per mask + NL, no spectrum" % (inputs.SEED_BASE + 2),
+                   "n": n, "m": m, "masks": (1 << m) - 1, "nl": nl_val},
+        "roofline": {"bound": "alu", "achieved": achieved_tops, "peak": PEAK_PK16_TOPS, "unit": "TOP/s",
+                     "frac": achieved_tops / PEAK_PK16_TOPS, "traffic": None,
+                     "kernel": "k_walsh<16,8,0>", "kernel_ms": ev_mean,
+                     "int32_valu_peak": PEAK_INT32_TOPS,
+                     "int32_valu_frac": achieved_tops / PEAK_INT32_TOPS},
+    }
+    if args.batched:
+        out["batched"] = bench_batched(torch, B, inputs, dev)
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(S_host, n, m, args.cpu_sample_masks)
+    print(json.dumps(out), flush=True)
+
+
+def bench_batched(torch, B, inputs, dev, reps=5):
+    """4096 mixed boxes (n = m in {6,8,10,12}): one planned batched launch vs a
+    loop of single-box calls on one stream."""
+    batch = inputs.workload_batched()
+    tabs = [B.table_to_device(S, n, device=dev) for n, S in batch]
+    ns = [n for n, _ in batch]
+    plan = B.Plan(tabs, ns, ns)
+    stream = torch.cuda.current_stream(dev)
+    plan.launch()
+    torch.cuda.synchronize(dev)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.launch()
+    g.replay()
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g.replay()
+    torch.cuda.synchronize(dev)
+    t_batch = (time.perf_counter() - t0) / reps
+    # plain loop: one sbox_walsh_nl_ex per box
+    nl = torch.empty(1, dtype=torch.int32, device=dev)
+    outs = [torch.empty(1 << n, dtype=torch.int32, device=dev) for n in ns]
+    ws = B.Workspace(max(B.sbox_walsh_nl_workspace_bytes(n, n, 0) for n in ns), dev)
+    sptr = int(stream.cuda_stream)
+
+    def loop():
+        for t, n, o in zip(tabs, ns, outs):
+            B.sbox_walsh_nl_ex(t.data_ptr(), n, n, t.element_size(), o.data_ptr(), nl.data_ptr(), 0, 0,
+                               ws.ptr, ws.nbytes, None, sptr)
+    loop()
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    loop()
+    torch.cuda.synchronize(dev)
+    t_loop = time.perf_counter() - t0
+    coeffs = sum((1 << n) * ((1 << n) - 1) for n in ns)
+    plan.close()
+    return {"boxes": len(batch), "sboxes_per_s": len(batch) / t_batch, "ms": t_batch * 1e3,
+            "coeff_per_s": coeffs / t_batch, "plain_loop_ms": t_loop * 1e3,
+            "plain_loop_sboxes_per_s": len(batch) / t_loop, "speedup_vs_plain_loop": t_loop / t_batch}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,173 @@
+/*
+ * sbox_walsh.h -- C ABI of the MI355X (gfx950) S-box Walsh spectrum /
+ * nonlinearity library (libsboxwalsh.so).
+ *
+ * What is computed (Khadem & Ghasemi, "Improved Algorithms in Parallel
+ * Evaluation of Large Cryptographic S-Box"):
+ *   - For an n x m S-box S (a table S[0 .. 2^n) of values whose low m bits
+ *     are used; Section 3, the vectorial Boolean function s = (f_1..f_m)),
+ *     the Walsh matrix of Eq. 1, with its exponent read as <a,x> + <b,S(x)>:
+ *         W(a, b) = sum_x (-1)^( parity(a & x) XOR parity(b & S[x]) ),
+ *     a in [0, 2^n), b in [0, 2^m).  Column b is the fast Walsh-Hadamard
+ *     transform (Algorithm 1) of the polarity truth table of the component
+ *     function x -> parity(b & S[x]) (Eq. 2), 0 -> +1, 1 -> -1, in natural
+ *     (Sylvester) order, so output index == a.
+ *   - The per-mask maximum maxabs[b] = max_a |W(a, b)| folded into the
+ *     transform (Algorithm 3, the "var" array), and the nonlinearity of
+ *     Eq. 3 over the nonzero masks (Algorithm 6):
+ *         NL = min_{b=1}^{2^m-1} (2^n - maxabs[b]) / 2
+ *            = 2^(n-1) - max_{b != 0, a} |W(a, b)| / 2.
+ *     maxabs[0] is 2^n by definition (row b = 0 is 2^n at a = 0, else 0).
+ *   - Optionally the whole matrix, written as int32 in one of two layouts:
+ *     SBOX_SPECTRUM_B_MAJOR: W[b * 2^n + a] (the transposed matrix of
+ *     Section 5.1) or SBOX_SPECTRUM_A_MAJOR: W[a * 2^m + b] (Algorithm 1's
+ *     matrix).  Without it the 2^(n+m) matrix is never materialised.
+ *   Every result is an exact integer; int32 holds all of them for n <= 30.
+ *
+ * Conventions for every entry point:
+ *   - Asynchronous: work is enqueued on `stream` (a hipStream_t; NULL is
+ *     the null stream) and results are valid after the stream is
+ *     synchronised.  Unless stated otherwise a call performs no host
+ *     synchronisation.
+ *   - Device pointers: S, maxabs_per_b, nl, spectrum and workspace are
+ *     device memory owned by the caller; the library never frees them.
+ *     They must be naturally aligned for their element type (workspace:
+ *     256 bytes).  S must stay unchanged until the work completes.
+ *   - Arguments are validated before anything is enqueued; on any error
+ *     nothing is enqueued, outputs are untouched, and the status is
+ *     returned with a message available from sbox_last_error().
+ *   - Limits: 1 <= n <= 24, 1 <= m <= 24, n + m <= 40.  Requests for a
+ *     spectrum need n + m <= 34.  Outside these: SBOX_ERR_UNSUPPORTED.
+ *   - Calls that share a workspace must not overlap in time (serialise them
+ *     on one stream).
+ */
+#ifndef SBOX_WALSH_H
+#define SBOX_WALSH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SBOX_OK = 0,
+    SBOX_ERR_INVALID_ARG = 1, /* null pointer, bad element width, bad layout, count < 0 ... */
+    SBOX_ERR_UNSUPPORTED = 2, /* n or m outside the limits above */
+    SBOX_ERR_WORKSPACE = 3,   /* workspace missing or smaller than the query says */
+    SBOX_ERR_HIP = 4          /* a HIP runtime call or kernel launch failed */
+} sbox_status;
+
+typedef enum {
+    SBOX_SPECTRUM_NONE = 0,
+    SBOX_SPECTRUM_B_MAJOR = 1, /* W[b * 2^n + a] */
+    SBOX_SPECTRUM_A_MAJOR = 2  /* W[a * 2^m + b] */
+} sbox_layout;
+
+/*
+ * Launch tuning.  Zero fields mean "library default".  Values that do not
+ * apply to the (n, m) at hand are rejected with SBOX_ERR_INVALID_ARG.
+ *   split_p : bits of x each thread transforms in registers before the
+ *             one LDS exchange (6, 7 or 8; n <= 8 uses n and ignores this).
+ *   chunk   : consecutive masks (in Gray-code order) one thread group
+ *             walks per work item.
+ *   grid    : number of persistent workgroups (0: fill every CU).
+ */
+typedef struct sbox_tuning {
+    int32_t split_p;
+    int32_t chunk;
+    int32_t grid;
+    int32_t reserved;
+} sbox_tuning;
+
+/*
+ * Fused spectrum + nonlinearity of one S-box (Eq. 1-3, Algorithms 3 and 6).
+ *   S            device, 2^n elements; element width inferred from m:
+ *                uint8 if m <= 8, uint16 if m <= 16, else uint32.
+ *   maxabs_per_b device int32[2^m] receiving max_a |W(a,b)|, or NULL.
+ *   nl           device int32[1] receiving NL (required).
+ * Uses a scratch area owned by the library (one per device, grown on
+ * demand with hipMalloc and kept until the process ends), so the first
+ * call at a new size allocates and is not graph-capturable; use
+ * sbox_walsh_nl_ex with a caller workspace for capture.
+ */
+sbox_status sbox_walsh_nl(const void* S, int n, int m, int32_t* maxabs_per_b, int32_t* nl,
+                          void* stream);
+
+/*
+ * Full form.
+ *   s_elem_bytes  1, 2 or 4: width of the S elements (unsigned).
+ *   spectrum      device int32[2^(n+m)] when layout != SBOX_SPECTRUM_NONE,
+ *                 else ignored (may be NULL).
+ *   workspace     device scratch of at least
+ *                 sbox_walsh_nl_workspace_bytes(n, m, layout) bytes
+ *                 (256-byte aligned).  When n > 16 a larger workspace lets
+ *                 more masks be processed per pass.
+ *   tuning        NULL for defaults.
+ * Performs no allocation and no host synchronisation; graph-capturable.
+ */
+sbox_status sbox_walsh_nl_ex(const void* S, int n, int m, int s_elem_bytes,
+                             int32_t* maxabs_per_b, int32_t* nl,
+                             int32_t* spectrum, int layout,
+                             void* workspace, size_t workspace_bytes,
+                             const sbox_tuning* tuning, void* stream);
+
+/* Minimum workspace for sbox_walsh_nl_ex; 0 if (n, m, layout) is unsupported. */
+size_t sbox_walsh_nl_workspace_bytes(int n, int m, int layout);
+
+/*
+ * One S-box of a batch.  Same meaning as the arguments of
+ * sbox_walsh_nl_ex; batched boxes must have n <= 16.
+ */
+typedef struct sbox_job {
+    const void* S;
+    int32_t n, m, s_elem_bytes, layout;
+    int32_t* maxabs_per_b;
+    int32_t* nl;
+    int32_t* spectrum;
+} sbox_job;
+
+/*
+ * Many S-boxes of mixed sizes in one pass: boxes are grouped by n and each
+ * group runs as one persistent launch whose workgroups pull (box, mask
+ * range) items from a device work queue.  `jobs` is a host array of
+ * `count` entries; its descriptors are staged through a library-owned
+ * pinned host buffer and copied asynchronously, so the array may be reused
+ * as soon as the call returns.  Each box's results equal those of
+ * sbox_walsh_nl_ex on that box alone.  Returns SBOX_ERR_UNSUPPORTED if a
+ * box has n > 16.
+ */
+sbox_status sbox_walsh_nl_batched(const sbox_job* jobs, int32_t count,
+                                  void* workspace, size_t workspace_bytes, void* stream);
+
+/* Minimum workspace for sbox_walsh_nl_batched on these jobs; 0 if any is unsupported. */
+size_t sbox_batched_workspace_bytes(const sbox_job* jobs, int32_t count);
+
+/*
+ * Plans: the batch is analysed and its descriptors uploaded once, at
+ * creation (host call, synchronous, allocates device memory owned by the
+ * plan).  sbox_plan_launch then only enqueues kernels (no allocation, no
+ * host synchronisation, no copies), so it can be captured into a HIP graph
+ * and replayed; it reads the S tables at launch time.  The job array may
+ * be freed after sbox_plan_create returns; the buffers it points to must
+ * outlive the plan.  sbox_plan_destroy frees the plan's memory (it
+ * synchronises the device first).
+ */
+typedef struct sbox_plan sbox_plan;
+sbox_status sbox_plan_create(const sbox_job* jobs, int32_t count, const sbox_tuning* tuning,
+                             sbox_plan** out);
+sbox_status sbox_plan_launch(const sbox_plan* plan, void* stream);
+void sbox_plan_destroy(sbox_plan* plan);
+
+/* Text describing the last non-OK status returned on this thread ("" if none). */
+const char* sbox_last_error(void);
+
+/* Library version, e.g. "1.0.0". */
+const char* sbox_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SBOX_WALSH_H */

@@ -1,0 +1,692 @@
+// sbox_walsh.hip -- host side of libsboxwalsh.so: argument checks, launch
+// planning, workspaces, batching and plans.  The kernels live in
+// walsh_kernels.hpp; the ABI is declared in include/sbox_walsh.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "sbox_walsh.h"
+#include "walsh_kernels.hpp"
+
+using namespace sbw;
+
+namespace {
+
+// ---------------------------------------------------------------- errors ---
+thread_local std::string g_last_error;
+
+sbox_status fail(sbox_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+sbox_status fail(sbox_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                    \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess) return fail(SBOX_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// ------------------------------------------------------------- kernels ----
+using KFn = void (*)(KParams);
+
+int default_split(int n) {
+  if (n <= 8) return n;
+  if (n <= 12) return 6;
+  if (n <= 14) return 7;
+  return 8;
+}
+
+bool split_valid(int n, int p) {
+  if (n <= 8) return p == n;
+  return p >= 6 && p <= 8 && n - p >= 1 && n - p <= p;
+}
+
+template <int N, int P>
+KFn pick_mode(int mode, bool any_p) {
+  if (mode == kMax) return &k_walsh<N, P, kMax>;
+  if (any_p) return nullptr;  // store modes exist for the default split only
+  if (mode == kStoreB) return &k_walsh<N, P, kStoreB>;
+  if (mode == kStoreA) return &k_walsh<N, P, kStoreA>;
+  return nullptr;
+}
+
+template <int N>
+KFn pick_big(int p, int mode) {
+  constexpr int D = (N <= 12) ? 6 : (N <= 14 ? 7 : 8);
+  const bool nd = p != D;
+  if constexpr (N <= 12) {
+    if (p == 6) return pick_mode<N, 6>(mode, nd);
+  }
+  if constexpr (N <= 14) {
+    if (p == 7) return pick_mode<N, 7>(mode, nd);
+  }
+  if (p == 8) return pick_mode<N, 8>(mode, nd);
+  return nullptr;
+}
+
+KFn lookup_kernel(int n, int p, int mode) {
+  switch (n) {
+    case 1: return pick_mode<1, 1>(mode, false);
+    case 2: return pick_mode<2, 2>(mode, false);
+    case 3: return pick_mode<3, 3>(mode, false);
+    case 4: return pick_mode<4, 4>(mode, false);
+    case 5: return pick_mode<5, 5>(mode, false);
+    case 6: return pick_mode<6, 6>(mode, false);
+    case 7: return pick_mode<7, 7>(mode, false);
+    case 8: return pick_mode<8, 8>(mode, false);
+    case 9: return pick_big<9>(p, mode);
+    case 10: return pick_big<10>(p, mode);
+    case 11: return pick_big<11>(p, mode);
+    case 12: return pick_big<12>(p, mode);
+    case 13: return pick_big<13>(p, mode);
+    case 14: return pick_big<14>(p, mode);
+    case 15: return pick_big<15>(p, mode);
+    case 16:
+      if (mode == kBlock) return p == 8 ? &k_walsh<16, 8, kBlock> : nullptr;
+      return pick_big<16>(p, mode);
+    default: return nullptr;
+  }
+}
+
+struct DevInfo {
+  int cus = 0;
+  std::map<const void*, int> occ;
+};
+std::mutex g_dev_mu;
+std::map<int, DevInfo> g_dev;
+
+sbox_status device_info(int* cus) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_dev_mu);
+  DevInfo& di = g_dev[dev];
+  if (di.cus == 0) HIP_TRY(hipDeviceGetAttribute(&di.cus, hipDeviceAttributeMultiprocessorCount, dev));
+  *cus = di.cus;
+  return SBOX_OK;
+}
+
+sbox_status occupancy(const void* fn, int* blocks_per_cu) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_dev_mu);
+  DevInfo& di = g_dev[dev];
+  auto it = di.occ.find(fn);
+  if (it == di.occ.end()) {
+    int nb = 0;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kWG, 0));
+    if (nb < 1) nb = 1;
+    it = di.occ.emplace(fn, nb).first;
+  }
+  *blocks_per_cu = it->second;
+  return SBOX_OK;
+}
+
+sbox_status launch(const void* fn, dim3 grid, dim3 block, void** args, hipStream_t st) {
+  HIP_TRY(hipLaunchKernel(fn, grid, block, args, 0, st));
+  return SBOX_OK;
+}
+
+// ------------------------------------------------------------ checking ----
+sbox_status check_nm(int n, int m) {
+  if (n < 1 || n > 24 || m < 1 || m > 24 || n + m > 40)
+    return fail(SBOX_ERR_UNSUPPORTED, "unsupported size n=%d m=%d (need 1<=n,m<=24, n+m<=40)", n, m);
+  return SBOX_OK;
+}
+
+sbox_status check_layout(int layout, int n, int m, const int32_t* spec) {
+  if (layout != SBOX_SPECTRUM_NONE && layout != SBOX_SPECTRUM_B_MAJOR && layout != SBOX_SPECTRUM_A_MAJOR)
+    return fail(SBOX_ERR_INVALID_ARG, "invalid spectrum layout %d", layout);
+  if (layout != SBOX_SPECTRUM_NONE) {
+    if (!spec) return fail(SBOX_ERR_INVALID_ARG, "spectrum layout %d requested with a null spectrum", layout);
+    if (n + m > 34) return fail(SBOX_ERR_UNSUPPORTED, "spectrum of 2^%d coefficients is too large", n + m);
+  }
+  return SBOX_OK;
+}
+
+int elem_bytes_for(int m) { return m <= 8 ? 1 : (m <= 16 ? 2 : 4); }
+
+size_t f_bytes(int n, int m) {
+  const size_t nwords = n >= 5 ? ((size_t)1 << (n - 5)) : 1;
+  return align256((size_t)m * nwords * 4);
+}
+
+constexpr size_t kQueueBytes = 256;  // 64 counters
+
+// n > 16: masks per pass that a workspace of `bytes` allows (0: too small).
+long long large_batch_for(int n, int m, size_t bytes) {
+  const size_t fixed = kQueueBytes + f_bytes(n, m);
+  if (bytes < fixed) return 0;
+  const size_t per_mask = ((size_t)4 << n) + 4;
+  long long b = (long long)((bytes - fixed - 256) / per_mask);
+  const long long M = 1LL << m;
+  return std::min(b, M);
+}
+
+long long default_large_batch(int n, int m) {
+  const long long b = std::max(1LL, (1LL << 26) >> n);
+  return std::min(b, 1LL << m);
+}
+
+size_t large_bytes(int n, int m, long long batch) {
+  return kQueueBytes + f_bytes(n, m) + align256(4 * (size_t)batch) + ((size_t)batch << n) * 4;
+}
+
+int mode_of(int layout) { return layout == 1 ? kStoreB : (layout == 2 ? kStoreA : kMax); }
+
+// Chunk and grid for a kernel with `groups` thread groups per workgroup over
+// `masks` masks per job x `njobs` jobs.
+void pick_chunk(long long masks_total, int groups, int grid_cap, int chunk_req, int* chunk) {
+  if (chunk_req > 0) {
+    *chunk = chunk_req;
+    return;
+  }
+  long long c = masks_total / ((long long)groups * grid_cap * 8);
+  c = std::max(1LL, std::min(64LL, c));
+  *chunk = (int)c;
+}
+
+// ------------------------------------------------------- one S-box call ----
+sbox_status run_single(const void* S, int n, int m, int eb, int32_t* maxabs, int32_t* nl, int32_t* spec,
+                       int layout, void* ws, size_t ws_bytes, const sbox_tuning* tun, hipStream_t st) {
+  int cus = 0;
+  sbox_status s = device_info(&cus);
+  if (s) return s;
+  int* queue = reinterpret_cast<int*>(ws);
+  uint32_t* F = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(ws) + kQueueBytes);
+  const int nwords = n >= 5 ? 1 << (n - 5) : 1;
+
+  // bit-sliced component words
+  {
+    const void* S_ = S;
+    int n_ = n, m_ = m, nw_ = nwords;
+    uint32_t* F_ = F;
+    void* args[] = {(void*)&S_, &n_, &m_, &F_, &nw_};
+    const void* fn = eb == 1 ? (const void*)&k_bitslice<1> : eb == 2 ? (const void*)&k_bitslice<2>
+                                                                     : (const void*)&k_bitslice<4>;
+    s = launch(fn, dim3((nwords + 255) / 256), dim3(256), args, st);
+    if (s) return s;
+  }
+  JobDesc jd{};
+  jd.S = S;
+  jd.F = F;
+  jd.maxabs = maxabs;
+  jd.nl = nl;
+  jd.spec = spec;
+  jd.item_begin = 0;
+  jd.n = n;
+  jd.m = m;
+  jd.nwords = nwords;
+  jd.s_elem_bytes = eb;
+  // init: queue counters, NL, maxabs[0], b = 0 spectrum row
+  {
+    const JobDesc* nulljobs = nullptr;
+    int one = 1, nq = 64, lay = layout;
+    void* args[] = {(void*)&nulljobs, &jd, &one, &queue, &nq, &lay};
+    s = launch((const void*)&k_init_jobs, dim3(1), dim3(256), args, st);
+    if (s) return s;
+  }
+
+  if (n <= 16) {
+    const int p = (tun && tun->split_p) ? tun->split_p : default_split(n);
+    const int mode = mode_of(layout);
+    if (n > 8 && !split_valid(n, p)) return fail(SBOX_ERR_INVALID_ARG, "split_p=%d invalid for n=%d", p, n);
+    KFn fn = lookup_kernel(n, n <= 8 ? n : p, mode);
+    if (!fn) return fail(SBOX_ERR_INVALID_ARG, "no kernel for n=%d split_p=%d layout=%d", n, p, layout);
+    int occ = 1;
+    s = occupancy((const void*)fn, &occ);
+    if (s) return s;
+    const int Q = n <= 8 ? 0 : n - p;
+    const int groups = kWG >> Q;
+    const long long M = 1LL << m;
+    int grid_cap = (tun && tun->grid) ? tun->grid : occ * cus;
+    int chunk = 1;
+    pick_chunk(M, groups, grid_cap, tun ? tun->chunk : 0, &chunk);
+    const long long per_item = (long long)groups * chunk;
+    KParams kp{};
+    kp.jobs = nullptr;
+    kp.job0 = jd;
+    kp.njobs = 1;
+    kp.chunk = chunk;
+    kp.queue = queue;
+    kp.total_items = (M + per_item - 1) / per_item;
+    const int grid = (int)std::min<long long>(grid_cap, kp.total_items);
+    void* args[] = {&kp};
+    return launch((const void*)fn, dim3(grid), dim3(kWG), args, st);
+  }
+
+  // ---- n > 16: 2^16-point block transforms, then the block-index stages
+  const long long M = 1LL << m;
+  long long batch = large_batch_for(n, m, ws_bytes);
+  if (batch < 1) return fail(SBOX_ERR_WORKSPACE, "workspace too small for n=%d", n);
+  char* base = reinterpret_cast<char*>(ws) + kQueueBytes + f_bytes(n, m);
+  int* slotmax = reinterpret_cast<int*>(base);
+  int32_t* T = reinterpret_cast<int32_t*>(base + align256(4 * (size_t)batch));
+  KFn fnA = lookup_kernel(16, 8, kBlock);
+  int occ = 1;
+  s = occupancy((const void*)fnA, &occ);
+  if (s) return s;
+  const int L = n - 16;
+  const int chunk = (tun && tun->chunk) ? tun->chunk : 4;
+  const int grid_cap = (tun && tun->grid) ? tun->grid : occ * cus;
+  for (long long kbase = 0; kbase < M; kbase += batch) {
+    const long long kcount = std::min(batch, M - kbase);
+    // zero this pass's counter and per-mask maxima
+    {
+      int* q1 = queue + 1;
+      long long one = 1;
+      void* a1[] = {&q1, &one};
+      s = launch((const void*)&k_zero, dim3(1), dim3(256), a1, st);
+      if (s) return s;
+      long long cnt = kcount;
+      void* a2[] = {&slotmax, &cnt};
+      s = launch((const void*)&k_zero, dim3((unsigned)std::min<long long>(1024, (kcount + 255) / 256)), dim3(256), a2, st);
+      if (s) return s;
+    }
+    KParams kp{};
+    kp.job0 = jd;
+    kp.njobs = 1;
+    kp.chunk = chunk;
+    kp.queue = queue + 1;
+    kp.total_items = ((kcount + chunk - 1) / chunk) << L;
+    kp.blockout = T;
+    kp.kbase = kbase;
+    kp.kcount = kcount;
+    kp.nblk_log = L;
+    {
+      const int grid = (int)std::min<long long>(grid_cap, kp.total_items);
+      void* args[] = {&kp};
+      s = launch((const void*)fnA, dim3(grid), dim3(kWG), args, st);
+      if (s) return s;
+    }
+    // block-index stages, up to 4 bits per pass
+    int bit0 = 0;
+    while (bit0 < L) {
+      const int r = std::min(4, L - bit0);
+      const bool last = bit0 + r == L;
+      const long long threads = kcount * ((1LL << 16) << (L - r));
+      const unsigned blocks = (unsigned)((threads + 255) / 256);
+      int32_t* spec_ = spec;
+      int lay = layout, m_ = m, L_ = L, b0 = bit0;
+      long long kc = kcount, kb = kbase, mend = M;
+      void* args[] = {&T, &kc, &L_, &b0, &slotmax, &spec_, &lay, &m_, &kb, &mend};
+      const void* fn = nullptr;
+      if (last) {
+        fn = r == 1 ? (const void*)&k_combine<1, true> : r == 2 ? (const void*)&k_combine<2, true>
+           : r == 3 ? (const void*)&k_combine<3, true> : (const void*)&k_combine<4, true>;
+      } else {
+        fn = (const void*)&k_combine<4, false>;
+      }
+      s = launch(fn, dim3(blocks), dim3(256), args, st);
+      if (s) return s;
+      bit0 += r;
+    }
+    {
+      long long kc = kcount, kb = kbase, mend = M;
+      int n_ = n;
+      int32_t* mx = maxabs;
+      int32_t* nl_ = nl;
+      void* args[] = {&slotmax, &kc, &kb, &mend, &n_, &mx, &nl_};
+      s = launch((const void*)&k_finalize_batch, dim3((unsigned)((kcount + 255) / 256)), dim3(256), args, st);
+      if (s) return s;
+    }
+  }
+  return SBOX_OK;
+}
+
+// --------------------------------------------------------------- batches ---
+struct ClassLaunch {
+  int n, layout;
+  KFn fn;
+  int njobs;
+  size_t desc_off;  // byte offset of this class's JobDesc table in the descriptor area
+  int chunk;
+  long long total_items;
+  int grid;
+};
+
+struct BatchLayout {
+  int count = 0;
+  size_t desc_bytes = 0;   // all JobDesc tables
+  size_t f_total = 0;      // all bit-sliced words
+  size_t ws_bytes = 0;     // queue + descs + F
+  std::vector<JobDesc> descs;  // host copy, F pointers relative to the F area (filled at bind)
+  std::vector<size_t> f_off;   // per desc, offset inside the F area
+  std::vector<ClassLaunch> classes;
+};
+
+sbox_status check_job(const sbox_job& j, int idx) {
+  if (!j.S || !j.nl) return fail(SBOX_ERR_INVALID_ARG, "job %d: null S or nl", idx);
+  if (j.s_elem_bytes != 1 && j.s_elem_bytes != 2 && j.s_elem_bytes != 4)
+    return fail(SBOX_ERR_INVALID_ARG, "job %d: s_elem_bytes must be 1, 2 or 4", idx);
+  sbox_status s = check_nm(j.n, j.m);
+  if (s) return s;
+  if (j.n > 16) return fail(SBOX_ERR_UNSUPPORTED, "job %d: batched boxes need n <= 16 (n=%d)", idx, j.n);
+  return check_layout(j.layout, j.n, j.m, j.spectrum);
+}
+
+sbox_status plan_batch(const sbox_job* jobs, int count, const sbox_tuning* tun, BatchLayout* out) {
+  if (count < 0 || (count > 0 && !jobs)) return fail(SBOX_ERR_INVALID_ARG, "bad job array");
+  if (count > (1 << 20)) return fail(SBOX_ERR_UNSUPPORTED, "too many jobs (%d)", count);
+  for (int i = 0; i < count; ++i) {
+    sbox_status s = check_job(jobs[i], i);
+    if (s) return s;
+  }
+  int cus = 0;
+  sbox_status s = device_info(&cus);
+  if (s) return s;
+  BatchLayout L;
+  L.count = count;
+  // classes keyed by (n desc, layout); jobs inside by descending m (largest work first)
+  std::vector<int> order(count);
+  for (int i = 0; i < count; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    if (jobs[a].n != jobs[b].n) return jobs[a].n > jobs[b].n;
+    if (jobs[a].layout != jobs[b].layout) return jobs[a].layout < jobs[b].layout;
+    return jobs[a].m > jobs[b].m;
+  });
+  size_t f_off = 0;
+  int i = 0;
+  while (i < count) {
+    const int n = jobs[order[i]].n, layout = jobs[order[i]].layout;
+    int jend = i;
+    while (jend < count && jobs[order[jend]].n == n && jobs[order[jend]].layout == layout) ++jend;
+    ClassLaunch c{};
+    c.n = n;
+    c.layout = layout;
+    const int p = (tun && tun->split_p && n > 8) ? tun->split_p : default_split(n);
+    if (n > 8 && !split_valid(n, p)) return fail(SBOX_ERR_INVALID_ARG, "split_p=%d invalid for n=%d", p, n);
+    c.fn = lookup_kernel(n, p, mode_of(layout));
+    if (!c.fn) return fail(SBOX_ERR_INVALID_ARG, "no kernel for n=%d split_p=%d layout=%d", n, p, layout);
+    int occ = 1;
+    s = occupancy((const void*)c.fn, &occ);
+    if (s) return s;
+    const int Q = n <= 8 ? 0 : n - p;
+    const int groups = kWG >> Q;
+    const int grid_cap = (tun && tun->grid) ? tun->grid : occ * cus;
+    long long masks_total = 0;
+    for (int k = i; k < jend; ++k) masks_total += 1LL << jobs[order[k]].m;
+    pick_chunk(masks_total, groups, grid_cap, tun ? tun->chunk : 0, &c.chunk);
+    c.njobs = jend - i;
+    c.desc_off = L.descs.size() * sizeof(JobDesc);
+    long long items = 0;
+    for (int k = i; k < jend; ++k) {
+      const sbox_job& j = jobs[order[k]];
+      JobDesc d{};
+      d.S = j.S;
+      d.maxabs = j.maxabs_per_b;
+      d.nl = j.nl;
+      d.spec = j.layout ? j.spectrum : nullptr;
+      d.item_begin = items;
+      d.n = j.n;
+      d.m = j.m;
+      d.nwords = j.n >= 5 ? 1 << (j.n - 5) : 1;
+      d.s_elem_bytes = j.s_elem_bytes;
+      const long long per_item = (long long)groups * c.chunk;
+      items += ((1LL << j.m) + per_item - 1) / per_item;
+      L.descs.push_back(d);
+      L.f_off.push_back(f_off);
+      f_off += f_bytes(j.n, j.m);
+    }
+    c.total_items = items;
+    if (items >= (1LL << 31)) return fail(SBOX_ERR_UNSUPPORTED, "batch too large");
+    c.grid = (int)std::min<long long>(grid_cap, items);
+    L.classes.push_back(c);
+    i = jend;
+  }
+  if (L.classes.size() > 60) return fail(SBOX_ERR_UNSUPPORTED, "too many size classes");
+  L.desc_bytes = align256(L.descs.size() * sizeof(JobDesc));
+  L.f_total = f_off;
+  L.ws_bytes = kQueueBytes + L.desc_bytes + L.f_total;
+  *out = std::move(L);
+  return SBOX_OK;
+}
+
+// Fill F pointers for a workspace at `ws` (descs are copied to ws + kQueueBytes).
+void bind_batch(BatchLayout& L, void* ws) {
+  char* fbase = reinterpret_cast<char*>(ws) + kQueueBytes + L.desc_bytes;
+  for (size_t k = 0; k < L.descs.size(); ++k) L.descs[k].F = reinterpret_cast<const uint32_t*>(fbase + L.f_off[k]);
+}
+
+sbox_status launch_batch(const BatchLayout& L, void* ws, hipStream_t st) {
+  if (L.count == 0) return SBOX_OK;
+  int* queue = reinterpret_cast<int*>(ws);
+  const JobDesc* dtab = reinterpret_cast<const JobDesc*>(reinterpret_cast<char*>(ws) + kQueueBytes);
+  sbox_status s;
+  // bit-slice every table (grid.y <= 65535 jobs per launch)
+  for (int j0 = 0; j0 < L.count; j0 += 65535) {
+    const int nj = std::min(65535, L.count - j0);
+    const JobDesc* d = dtab + j0;
+    void* args[] = {(void*)&d};
+    s = launch((const void*)&k_bitslice_jobs, dim3(8, nj), dim3(256), args, st);
+    if (s) return s;
+  }
+  // per-job init (NL start value, maxabs[0], b = 0 spectrum row), then the queue counters
+  for (const ClassLaunch& c : L.classes) {
+    const JobDesc* d = reinterpret_cast<const JobDesc*>(reinterpret_cast<const char*>(dtab) + c.desc_off);
+    JobDesc unused{};
+    int njc = c.njobs, nq0 = 0, lay = c.layout;
+    void* args[] = {(void*)&d, &unused, &njc, &queue, &nq0, &lay};
+    s = launch((const void*)&k_init_jobs, dim3(njc), dim3(256), args, st);
+    if (s) return s;
+  }
+  {
+    long long cnt = 64;
+    void* args[] = {&queue, &cnt};
+    s = launch((const void*)&k_zero, dim3(1), dim3(256), args, st);
+    if (s) return s;
+  }
+  int ci = 0;
+  for (const ClassLaunch& c : L.classes) {
+    KParams kp{};
+    kp.jobs = reinterpret_cast<const JobDesc*>(reinterpret_cast<const char*>(dtab) + c.desc_off);
+    kp.njobs = c.njobs;
+    kp.chunk = c.chunk;
+    kp.queue = queue + ci;
+    kp.total_items = c.total_items;
+    void* args[] = {&kp};
+    s = launch((const void*)c.fn, dim3(c.grid), dim3(kWG), args, st);
+    if (s) return s;
+    ++ci;
+  }
+  return SBOX_OK;
+}
+
+// ------------------------------------------------- pinned staging buffer ---
+std::mutex g_stage_mu;
+void* g_stage = nullptr;
+size_t g_stage_bytes = 0;
+hipEvent_t g_stage_evt = nullptr;
+bool g_stage_pending = false;
+
+// ------------------------------------------------- library-owned scratch ---
+struct Scratch {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+std::mutex g_scratch_mu;
+std::map<int, Scratch> g_scratch;
+
+}  // namespace
+
+// ===================================================================== ABI ==
+extern "C" {
+
+const char* sbox_last_error(void) { return g_last_error.c_str(); }
+
+const char* sbox_version(void) { return "1.0.0"; }
+
+size_t sbox_walsh_nl_workspace_bytes(int n, int m, int layout) {
+  if (n < 1 || n > 24 || m < 1 || m > 24 || n + m > 40) return 0;
+  if (layout < 0 || layout > 2) return 0;
+  if (layout != 0 && n + m > 34) return 0;
+  if (n <= 16) return kQueueBytes + f_bytes(n, m);
+  return large_bytes(n, m, default_large_batch(n, m));
+}
+
+sbox_status sbox_walsh_nl_ex(const void* S, int n, int m, int s_elem_bytes, int32_t* maxabs_per_b,
+                             int32_t* nl, int32_t* spectrum, int layout, void* workspace,
+                             size_t workspace_bytes, const sbox_tuning* tuning, void* stream) {
+  sbox_status s = check_nm(n, m);
+  if (s) return s;
+  if (!S) return fail(SBOX_ERR_INVALID_ARG, "S is null");
+  if (!nl) return fail(SBOX_ERR_INVALID_ARG, "nl is null");
+  if (s_elem_bytes != 1 && s_elem_bytes != 2 && s_elem_bytes != 4)
+    return fail(SBOX_ERR_INVALID_ARG, "s_elem_bytes must be 1, 2 or 4 (got %d)", s_elem_bytes);
+  s = check_layout(layout, n, m, spectrum);
+  if (s) return s;
+  if (tuning) {
+    if (tuning->chunk < 0 || tuning->grid < 0 || tuning->split_p < 0)
+      return fail(SBOX_ERR_INVALID_ARG, "negative tuning field");
+    if (tuning->split_p && n > 8 && n <= 16 && !split_valid(n, tuning->split_p))
+      return fail(SBOX_ERR_INVALID_ARG, "split_p=%d invalid for n=%d", tuning->split_p, n);
+    if (tuning->split_p && n <= 16 && n > 8 && layout != 0 && tuning->split_p != default_split(n))
+      return fail(SBOX_ERR_INVALID_ARG, "spectrum output uses split_p=%d for n=%d", default_split(n), n);
+  }
+  const size_t need = sbox_walsh_nl_workspace_bytes(n, m, layout);
+  if (!workspace) return fail(SBOX_ERR_WORKSPACE, "workspace is null (need %zu bytes)", need);
+  if (reinterpret_cast<uintptr_t>(workspace) & 255) return fail(SBOX_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+  if (n <= 16 && workspace_bytes < need)
+    return fail(SBOX_ERR_WORKSPACE, "workspace of %zu bytes, need %zu", workspace_bytes, need);
+  if (n > 16 && large_batch_for(n, m, workspace_bytes) < 1)
+    return fail(SBOX_ERR_WORKSPACE, "workspace of %zu bytes too small for n=%d (need >= %zu)", workspace_bytes, n,
+                large_bytes(n, m, 1));
+  return run_single(S, n, m, s_elem_bytes, maxabs_per_b, nl, spectrum, layout, workspace, workspace_bytes,
+                    tuning, reinterpret_cast<hipStream_t>(stream));
+}
+
+sbox_status sbox_walsh_nl(const void* S, int n, int m, int32_t* maxabs_per_b, int32_t* nl, void* stream) {
+  sbox_status s = check_nm(n, m);
+  if (s) return s;
+  if (!S || !nl) return fail(SBOX_ERR_INVALID_ARG, "S or nl is null");
+  const size_t need = sbox_walsh_nl_workspace_bytes(n, m, 0);
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  void* ws = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    Scratch& sc = g_scratch[dev];
+    if (sc.bytes < need) {
+      if (sc.ptr) {
+        HIP_TRY(hipDeviceSynchronize());
+        HIP_TRY(hipFree(sc.ptr));
+        sc.ptr = nullptr;
+        sc.bytes = 0;
+      }
+      HIP_TRY(hipMalloc(&sc.ptr, need));
+      sc.bytes = need;
+    }
+    ws = sc.ptr;
+    return sbox_walsh_nl_ex(S, n, m, elem_bytes_for(m), maxabs_per_b, nl, nullptr, 0, ws, sc.bytes, nullptr,
+                            stream);
+  }
+}
+
+size_t sbox_batched_workspace_bytes(const sbox_job* jobs, int32_t count) {
+  BatchLayout L;
+  std::string keep = g_last_error;
+  if (plan_batch(jobs, count, nullptr, &L) != SBOX_OK) {
+    g_last_error = keep;
+    return 0;
+  }
+  return L.ws_bytes;
+}
+
+sbox_status sbox_walsh_nl_batched(const sbox_job* jobs, int32_t count, void* workspace, size_t workspace_bytes,
+                                  void* stream) {
+  BatchLayout L;
+  sbox_status s = plan_batch(jobs, count, nullptr, &L);
+  if (s) return s;
+  if (count == 0) return SBOX_OK;
+  if (!workspace || workspace_bytes < L.ws_bytes)
+    return fail(SBOX_ERR_WORKSPACE, "workspace of %zu bytes, need %zu", workspace_bytes, L.ws_bytes);
+  if (reinterpret_cast<uintptr_t>(workspace) & 255) return fail(SBOX_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+  bind_batch(L, workspace);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  {
+    std::lock_guard<std::mutex> lk(g_stage_mu);
+    const size_t bytes = L.descs.size() * sizeof(JobDesc);
+    if (g_stage_pending) {
+      HIP_TRY(hipEventSynchronize(g_stage_evt));
+      g_stage_pending = false;
+    }
+    if (g_stage_bytes < bytes) {
+      if (g_stage) HIP_TRY(hipHostFree(g_stage));
+      g_stage = nullptr;
+      g_stage_bytes = 0;
+      HIP_TRY(hipHostMalloc(&g_stage, bytes, hipHostMallocDefault));
+      g_stage_bytes = bytes;
+    }
+    if (!g_stage_evt) HIP_TRY(hipEventCreateWithFlags(&g_stage_evt, hipEventDisableTiming));
+    std::memcpy(g_stage, L.descs.data(), bytes);
+    HIP_TRY(hipMemcpyAsync(reinterpret_cast<char*>(workspace) + kQueueBytes, g_stage, bytes, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipEventRecord(g_stage_evt, st));
+    g_stage_pending = true;
+  }
+  return launch_batch(L, workspace, st);
+}
+
+struct sbox_plan {
+  BatchLayout layout;
+  void* dev = nullptr;
+};
+
+sbox_status sbox_plan_create(const sbox_job* jobs, int32_t count, const sbox_tuning* tuning, sbox_plan** out) {
+  if (!out) return fail(SBOX_ERR_INVALID_ARG, "out is null");
+  *out = nullptr;
+  if (tuning && (tuning->chunk < 0 || tuning->grid < 0 || tuning->split_p < 0))
+    return fail(SBOX_ERR_INVALID_ARG, "negative tuning field");
+  sbox_plan* p = new sbox_plan();
+  sbox_status s = plan_batch(jobs, count, tuning, &p->layout);
+  if (s) {
+    delete p;
+    return s;
+  }
+  if (count > 0) {
+    hipError_t e = hipMalloc(&p->dev, p->layout.ws_bytes);
+    if (e != hipSuccess) {
+      delete p;
+      return fail(SBOX_ERR_HIP, "hipMalloc(%zu): %s", p->layout.ws_bytes, hipGetErrorString(e));
+    }
+    bind_batch(p->layout, p->dev);
+    e = hipMemcpy(reinterpret_cast<char*>(p->dev) + kQueueBytes, p->layout.descs.data(),
+                  p->layout.descs.size() * sizeof(JobDesc), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      (void)hipFree(p->dev);
+      delete p;
+      return fail(SBOX_ERR_HIP, "hipMemcpy: %s", hipGetErrorString(e));
+    }
+  }
+  *out = p;
+  return SBOX_OK;
+}
+
+sbox_status sbox_plan_launch(const sbox_plan* plan, void* stream) {
+  if (!plan) return fail(SBOX_ERR_INVALID_ARG, "plan is null");
+  return launch_batch(plan->layout, plan->dev, reinterpret_cast<hipStream_t>(stream));
+}
+
+void sbox_plan_destroy(sbox_plan* plan) {
+  if (!plan) return;
+  if (plan->dev) {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(plan->dev);
+  }
+  delete plan;
+}
+
+}  // extern "C"

@@ -1,0 +1,579 @@
+// walsh_kernels.hpp -- gfx950 kernels for the fused S-box Walsh transform.
+//
+// One column of the Walsh matrix (Eq. 1) per nonzero output mask b is the
+// length-2^n fast Walsh-Hadamard transform (Algorithm 1) of the polarity
+// truth table of x -> parity(b & S[x]) (Eq. 2).  The per-mask maximum of
+// |W| is folded into the last butterfly stage (Algorithm 3) and the minimum
+// over masks (Algorithm 6) into a device atomic, so the 2^(n+m) matrix is
+// only written when a spectrum layout is requested.
+//
+// How the work maps onto CDNA4 (wave64, 256-thread workgroups):
+//
+//  * Bit-sliced component tables.  F[i][w] holds bit i of S[32w .. 32w+31]
+//    as one 32-bit word, so the 32 polarity bits of mask b over a word are
+//    G_b[w] = XOR_{i in b} F[i][w].  A thread group walks its masks in
+//    Gray-code order, so moving to the next mask costs one XOR per word.
+//
+//  * Five butterfly stages for the price of a popcount.  For the 32 inputs
+//    x' of one word, the 32-point transform of (-1)^g at output a' equals
+//    32 - 2 * popcount(G ^ L(a')), where L(a') is the truth table of
+//    x' -> parity(a' & x').  The kernel carries c'(a') = popcount - 16, so
+//    that every later value is exactly -W/2 (no correction at a = 0).
+//
+//  * Packed 16-bit arithmetic.  c' lies in [-16, 16] and each later stage
+//    at most doubles it, so after all n <= 16 stages |value| <= 2^15.  Two
+//    values share one VGPR (v_pk_add_u16 / v_pk_sub_u16), wrapping mod 2^16.
+//    Only +-32768 collide under the wrap (n = 16), and they have the same
+//    magnitude, so max |value| is still exact when tracked as
+//    max(max_i16, -min_i16) in 32 bits.  Modes that store values do the
+//    last stage in 32-bit instead.
+//
+//  * Register / LDS split.  x = (x_hi : Q bits, x_lo : P bits).  Phase 1:
+//    a thread owns one x_hi and all 2^P x_lo values (2^(P-1) packed VGPRs)
+//    and runs the popcount stages plus the P - 5 remaining low stages in
+//    registers.  One LDS transpose then gives each thread all x_hi values
+//    for some low outputs and phase 2 runs the Q high stages in registers.
+//    When Q == P the last high bit lives on lane bit 5 and is brought into
+//    registers with v_permlane32_swap.  n <= 8 needs no exchange at all:
+//    one lane owns one mask.
+//
+//  * Persistent workgroups pull items from a device counter; an item is a
+//    run of consecutive Gray-code indices for each thread group of the
+//    workgroup.  Batched launches use the same kernels with a job table.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sbw {
+
+constexpr int kWG = 256;  // threads per workgroup (4 waves)
+
+enum Mode : int { kMax = 0, kStoreB = 1, kStoreA = 2, kBlock = 3 };
+
+// One S-box evaluation as the kernels see it.
+struct JobDesc {
+  const void* S;         // table, s_elem_bytes per entry
+  const uint32_t* F;     // bit-sliced component words, [m][nwords]
+  int32_t* maxabs;       // 2^m entries or null
+  int32_t* nl;           // 1 entry
+  int32_t* spec;         // spectrum (layout per kernel mode) or null
+  long long item_begin;  // first queue item of this job (batched launches)
+  int n, m;
+  int nwords;            // words per slice (2^(n-5), at least 1)
+  int s_elem_bytes;
+};
+
+struct KParams {
+  const JobDesc* jobs;   // device job table, or null to use job0
+  JobDesc job0;
+  int njobs;
+  int chunk;             // Gray indices per thread group per item
+  int* queue;            // work counter, zero before the launch
+  long long total_items;
+  // n > 16, first pass: 2^16-point transforms of the 2^(n-16) blocks of x
+  int32_t* blockout;     // [kcount][2^n] int32
+  long long kbase;       // first Gray index of this batch of masks
+  long long kcount;      // masks in this batch
+  int nblk_log;          // n - 16
+};
+
+typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));
+typedef int16_t s16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint32_t pk_add(uint32_t a, uint32_t b) {
+  return __builtin_bit_cast(uint32_t, __builtin_bit_cast(u16x2, a) + __builtin_bit_cast(u16x2, b));
+}
+__device__ __forceinline__ uint32_t pk_sub(uint32_t a, uint32_t b) {
+  return __builtin_bit_cast(uint32_t, __builtin_bit_cast(u16x2, a) - __builtin_bit_cast(u16x2, b));
+}
+
+// Truth table of x' -> parity(a & x') over the 32 positions of a word.
+__host__ __device__ constexpr uint32_t walsh_mask(int a) {
+  return ((a & 1) ? 0xAAAAAAAAu : 0u) ^ ((a & 2) ? 0xCCCCCCCCu : 0u) ^ ((a & 4) ? 0xF0F0F0F0u : 0u) ^
+         ((a & 8) ? 0xFF00FF00u : 0u) ^ ((a & 16) ? 0xFFFF0000u : 0u);
+}
+
+__host__ __device__ constexpr long long gray(long long k) { return k ^ (k >> 1); }
+
+// Running max / min of packed int16 outputs.
+struct Tracker {
+  s16x2 hi, lo;
+  __device__ __forceinline__ void reset() {
+    hi = s16x2{-32768, -32768};
+    lo = s16x2{32767, 32767};
+  }
+  __device__ __forceinline__ void add(uint32_t v) {
+    const s16x2 s = __builtin_bit_cast(s16x2, v);
+    hi = __builtin_elementwise_max(hi, s);
+    lo = __builtin_elementwise_min(lo, s);
+  }
+  // max |value| in 32-bit; -(-32768) = 32768 is representable here.
+  __device__ __forceinline__ int result() const {
+    const int a = max((int)hi.x, (int)hi.y);
+    const int b = -min((int)lo.x, (int)lo.y);
+    return max(a, b);
+  }
+};
+
+// 2^(P-1) packed registers; butterfly on register index bit `bit`.
+template <int NR>
+__device__ __forceinline__ void stage_regs(uint32_t (&R)[NR], int bit) {
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    if (r & bit) continue;
+    const uint32_t u = R[r], v = R[r | bit];
+    R[r] = pk_add(u, v);
+    R[r | bit] = pk_sub(u, v);
+  }
+}
+
+// Lanes 0-31 keep A and receive B's lanes 0-31 ... : v_permlane32_swap exchanges
+// the upper 32 lanes of the first operand with the lower 32 lanes of the second.
+__device__ __forceinline__ void swap_halves(uint32_t& a, uint32_t& b) {
+  auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+  a = r[0];
+  b = r[1];
+}
+
+__device__ __forceinline__ int unpack_lo(uint32_t v) { return (int)(int16_t)(v & 0xFFFFu); }
+__device__ __forceinline__ int unpack_hi(uint32_t v) { return (int)v >> 16; }
+
+// Output index of low register u, half h (phase-1 packing: register bits 0-3
+// are a0..a3, the half is a4, register bits 4.. are a5..).
+__device__ __forceinline__ uint32_t aidx(int u, int h) {
+  return (uint32_t)((u & 15) | (h << 4) | ((u >> 4) << 5));
+}
+
+template <int NW>
+__device__ __forceinline__ void load_words(uint32_t (&G)[NW], const uint32_t* p, bool x0r) {
+  if constexpr (NW >= 4) {
+#pragma unroll
+    for (int i = 0; i < NW; i += 4) {
+      const uint4 v = *reinterpret_cast<const uint4*>(p + i);
+      if (x0r) {
+        G[i] ^= v.x; G[i + 1] ^= v.y; G[i + 2] ^= v.z; G[i + 3] ^= v.w;
+      } else {
+        G[i] = v.x; G[i + 1] = v.y; G[i + 2] = v.z; G[i + 3] = v.w;
+      }
+    }
+  } else if constexpr (NW == 2) {
+    const uint2 v = *reinterpret_cast<const uint2*>(p);
+    if (x0r) { G[0] ^= v.x; G[1] ^= v.y; } else { G[0] = v.x; G[1] = v.y; }
+  } else {
+    if (x0r) G[0] ^= p[0]; else G[0] = p[0];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Main fused kernel, n <= 16 (MODE kBlock: one 2^16 block of a larger n).
+// ---------------------------------------------------------------------------
+template <int N, int P_, int MODE>
+__global__ __launch_bounds__(kWG) void k_walsh(const KParams kp) {
+  constexpr int P = (N <= 8) ? N : P_;
+  constexpr int Q = N - P;
+  static_assert(Q >= 0 && Q <= P, "bad split");
+  static_assert(N <= 8 || (P >= 6 && P <= 8), "bad split");
+  constexpr int NW = (N >= 5) ? (1 << (P - 5)) : 1;   // words per thread
+  constexpr int NR = (N >= 5) ? NW * 16 : 1;          // packed registers
+  constexpr int GPW = kWG >> Q;                       // thread groups per workgroup
+  constexpr bool STORE = MODE != kMax;
+  constexpr int SWZ_SHIFT = (Q >= 1 && Q <= P - 1) ? (P - 1 - Q) : 0;
+  constexpr int U2 = (Q >= 1 && Q <= P - 1) ? (1 << (P - 1 - Q)) : 1;
+
+  __shared__ uint32_t lds[(Q > 0) ? NR * kWG : 1];
+  __shared__ int red[kWG / 64];
+  __shared__ long long s_item;
+
+  const int tid = threadIdx.x;
+  const int g = tid >> Q;                 // thread group in this workgroup
+  const int tg = tid & ((1 << Q) - 1);    // thread within the group
+  const int lane = tid & 63;
+  const int C = kp.chunk;
+
+  for (;;) {
+    if (tid == 0) s_item = (long long)atomicAdd(kp.queue, 1);
+    __syncthreads();
+    const long long item = s_item;
+    __syncthreads();
+    if (item >= kp.total_items) break;
+
+    // ---- decode the item
+    JobDesc jd;
+    long long li;
+    int xblk = 0;
+    if constexpr (MODE == kBlock) {
+      jd = kp.job0;
+      xblk = (int)(item & ((1LL << kp.nblk_log) - 1));
+      li = item >> kp.nblk_log;
+    } else if (kp.jobs == nullptr) {
+      jd = kp.job0;
+      li = item;
+    } else {
+      int lo = 0, hi = kp.njobs - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (kp.jobs[mid].item_begin <= item) lo = mid; else hi = mid - 1;
+      }
+      jd = kp.jobs[lo];
+      li = item - jd.item_begin;
+    }
+    const long long kfirst = (MODE == kBlock ? kp.kbase : 0) + (li * GPW + g) * (long long)C;
+    const long long kend = (MODE == kBlock) ? (kp.kbase + kp.kcount) : (1LL << jd.m);
+    const long long wb = (MODE == kBlock ? ((long long)xblk << 11) : 0) + (long long)tg * NW;
+    const int n = jd.n;
+    int runmin = 0x7fffffff;
+    uint32_t G[NW];
+
+    for (int step = 0; step < C; ++step) {
+      const long long k = kfirst + step;
+      const bool inrange = k < kend;
+      // ---- component words of mask gray(k) (Gray-code walk)
+      if (step == 0) {
+#pragma unroll
+        for (int w = 0; w < NW; ++w) G[w] = 0;
+        if (inrange) {
+          const long long gk = gray(k);
+          for (int i = 0; i < jd.m; ++i)
+            if ((gk >> i) & 1) load_words<NW>(G, jd.F + (long long)i * jd.nwords + wb, true);
+        }
+      } else if (inrange) {
+        const int i = __builtin_ctzll((unsigned long long)k);
+        load_words<NW>(G, jd.F + (long long)i * jd.nwords + wb, true);
+      }
+      const bool valid = inrange && k != 0;
+      const uint32_t b = (uint32_t)gray(k);
+      const long long slot = k - kp.kbase;  // kBlock only
+
+      int mx = 0;
+      auto emit = [&](uint32_t a, int v) {  // v = -W(a,b)/2 (or the block value)
+        mx = max(mx, v < 0 ? -v : v);
+        if (valid) {
+          if constexpr (MODE == kStoreB) jd.spec[((size_t)b << N) | a] = -2 * v;
+          if constexpr (MODE == kStoreA) jd.spec[((size_t)a << jd.m) | b] = -2 * v;
+          if constexpr (MODE == kBlock)
+            kp.blockout[((size_t)slot << (16 + kp.nblk_log)) + ((size_t)xblk << 16) + a] = v;
+        }
+      };
+
+      if constexpr (N < 5) {
+        // ---- fewer than 32 inputs: the whole transform is popcounts
+        constexpr uint32_t low = (N == 0) ? 1u : ((1u << (1 << N)) - 1u);
+#pragma unroll
+        for (int a = 0; a < (1 << N); ++a) {
+          const int c = __builtin_popcount((G[0] ^ walsh_mask(a)) & low) - (1 << (N - 1));
+          emit((uint32_t)a, c);
+        }
+      } else {
+        // ---- phase 1: popcount stages (x0..x4) + register stages (x5..x_{P-1})
+        uint32_t R[NR];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+#pragma unroll
+          for (int a = 0; a < 16; ++a) {
+            const int c0 = __builtin_popcount(G[w] ^ walsh_mask(a)) - 16;
+            const int c1 = __builtin_popcount(G[w] ^ walsh_mask(a | 16)) - 16;
+            R[w * 16 + a] = __builtin_amdgcn_perm((uint32_t)c1, (uint32_t)c0, 0x05040100u);
+          }
+        }
+        constexpr int LAST1 = P - 2;  // highest register bit of phase 1
+        if constexpr (Q == 0) {
+          if constexpr (P == 5) {
+            if constexpr (STORE) {
+#pragma unroll
+              for (int r = 0; r < NR; ++r) {
+                emit(aidx(r, 0), unpack_lo(R[r]));
+                emit(aidx(r, 1), unpack_hi(R[r]));
+              }
+            } else {
+              Tracker t; t.reset();
+#pragma unroll
+              for (int r = 0; r < NR; ++r) t.add(R[r]);
+              mx = t.result();
+            }
+          } else {
+#pragma unroll
+            for (int d = 4; d < LAST1; ++d) stage_regs<NR>(R, 1 << d);
+            constexpr int fb = 1 << LAST1;
+            if constexpr (STORE) {
+#pragma unroll
+              for (int r = 0; r < NR; ++r) {
+                if (r & fb) continue;
+                const uint32_t u = R[r], v = R[r | fb];
+                emit(aidx(r, 0), unpack_lo(u) + unpack_lo(v));
+                emit(aidx(r, 1), unpack_hi(u) + unpack_hi(v));
+                emit(aidx(r | fb, 0), unpack_lo(u) - unpack_lo(v));
+                emit(aidx(r | fb, 1), unpack_hi(u) - unpack_hi(v));
+              }
+            } else {
+              Tracker t; t.reset();
+#pragma unroll
+              for (int r = 0; r < NR; ++r) {
+                if (r & fb) continue;
+                t.add(pk_add(R[r], R[r | fb]));
+                t.add(pk_sub(R[r], R[r | fb]));
+              }
+              mx = t.result();
+            }
+          }
+        } else {
+#pragma unroll
+          for (int d = 4; d <= LAST1; ++d) stage_regs<NR>(R, 1 << d);
+          // ---- LDS transpose: row u (low output pair), column = thread
+#pragma unroll
+          for (int u = 0; u < NR; ++u) lds[u * kWG + (tid ^ ((u >> SWZ_SHIFT) & 31))] = R[u];
+          __syncthreads();
+          if constexpr (Q <= P - 1) {
+            // thread (g, v): pairs u = v*U2 + j, all 2^Q high inputs
+#pragma unroll
+            for (int j = 0; j < U2; ++j) {
+              const int u = tg * U2 + j;
+              const int sw = tg & 31;
+#pragma unroll
+              for (int y = 0; y < (1 << Q); ++y)
+                R[j * (1 << Q) + y] = lds[u * kWG + (((g << Q) + y) ^ sw)];
+            }
+#pragma unroll
+            for (int d = 0; d < Q - 1; ++d) stage_regs<NR>(R, 1 << d);
+            constexpr int fb = 1 << (Q - 1);
+            if constexpr (STORE) {
+#pragma unroll
+              for (int r = 0; r < NR; ++r) {
+                if (r & fb) continue;
+                const int j = r >> Q, y = r & ((1 << Q) - 1);
+                const int u = tg * U2 + j;
+                const uint32_t uu = R[r], vv = R[r | fb];
+                emit(aidx(u, 0) | ((uint32_t)y << P), unpack_lo(uu) + unpack_lo(vv));
+                emit(aidx(u, 1) | ((uint32_t)y << P), unpack_hi(uu) + unpack_hi(vv));
+                emit(aidx(u, 0) | ((uint32_t)(y | fb) << P), unpack_lo(uu) - unpack_lo(vv));
+                emit(aidx(u, 1) | ((uint32_t)(y | fb) << P), unpack_hi(uu) - unpack_hi(vv));
+              }
+            } else {
+              Tracker t; t.reset();
+#pragma unroll
+              for (int r = 0; r < NR; ++r) {
+                if (r & fb) continue;
+                t.add(pk_add(R[r], R[r | fb]));
+                t.add(pk_sub(R[r], R[r | fb]));
+              }
+              mx = t.result();
+            }
+          } else {
+            // Q == P: thread (u, h) with h on lane bit 5
+            const int u = (tg & 31) | ((tg >> 6) << 5);
+            const int h = (tg >> 5) & 1;
+            constexpr int HALF = 1 << (Q - 1);
+            constexpr int H2 = 1 << (Q - 2);
+#pragma unroll
+            for (int i = 0; i < HALF; ++i)
+              R[i] = lds[u * kWG + (((g << Q) + h * HALF + i) ^ (u & 31))];
+#pragma unroll
+            for (int d = 0; d < Q - 1; ++d) stage_regs<NR>(R, 1 << d);
+#pragma unroll
+            for (int i = 0; i < H2; ++i) swap_halves(R[i], R[i + H2]);
+            if constexpr (STORE) {
+#pragma unroll
+              for (int i = 0; i < H2; ++i) {
+                const uint32_t uu = R[i], vv = R[i + H2];
+                const uint32_t ah = (uint32_t)(i + h * H2) << P;
+                const uint32_t top = 1u << (N - 1);
+                emit(aidx(u, 0) | ah, unpack_lo(uu) + unpack_lo(vv));
+                emit(aidx(u, 1) | ah, unpack_hi(uu) + unpack_hi(vv));
+                emit(aidx(u, 0) | ah | top, unpack_lo(uu) - unpack_lo(vv));
+                emit(aidx(u, 1) | ah | top, unpack_hi(uu) - unpack_hi(vv));
+              }
+            } else {
+              Tracker t; t.reset();
+#pragma unroll
+              for (int i = 0; i < H2; ++i) {
+                t.add(pk_add(R[i], R[i + H2]));
+                t.add(pk_sub(R[i], R[i + H2]));
+              }
+              mx = t.result();
+            }
+          }
+        }
+      }
+
+      // ---- per-mask maximum over the thread group
+      if constexpr (Q >= 1) {
+        constexpr int W = (Q < 6) ? (1 << Q) : 64;
+#pragma unroll
+        for (int o = 1; o < W; o <<= 1) mx = max(mx, __shfl_xor(mx, o, 64));
+      }
+      if constexpr (Q >= 7) {
+        if (lane == 0) red[tid >> 6] = mx;
+      }
+      if constexpr (Q >= 1) __syncthreads();  // LDS rows are rewritten by the next mask
+      if constexpr (Q >= 7) {
+        constexpr int WPG = 1 << (Q - 6);  // waves per group
+        int gm = 0;
+#pragma unroll
+        for (int w = 0; w < WPG; ++w) gm = max(gm, red[g * WPG + w]);
+        mx = gm;
+      }
+      if constexpr (MODE != kBlock) {
+        if (tg == 0 && valid) {
+          if (jd.maxabs) jd.maxabs[b] = 2 * mx;
+          runmin = min(runmin, (1 << (n - 1)) - mx);
+        }
+      }
+    }
+    if constexpr (MODE != kBlock) {
+      if (tg == 0 && runmin != 0x7fffffff) atomicMin(jd.nl, runmin);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Bit-slicing: F[i][w] = bit i of S[32w + j] at bit j (j < min(32, 2^n)).
+// ---------------------------------------------------------------------------
+template <int EB>
+__device__ __forceinline__ uint32_t load_entry(const void* S, long long x) {
+  if constexpr (EB == 1) return reinterpret_cast<const uint8_t*>(S)[x];
+  if constexpr (EB == 2) return reinterpret_cast<const uint16_t*>(S)[x];
+  return reinterpret_cast<const uint32_t*>(S)[x];
+}
+
+template <int EB>
+__device__ void bitslice_words(const void* S, int n, int m, uint32_t* F, int nwords, int w) {
+  const int bits = (n >= 5) ? 32 : (1 << n);
+  uint32_t v[32];
+#pragma unroll
+  for (int j = 0; j < 32; ++j) v[j] = (j < bits) ? load_entry<EB>(S, (long long)w * 32 + j) : 0u;
+  for (int i = 0; i < m; ++i) {
+    uint32_t word = 0;
+#pragma unroll
+    for (int j = 0; j < 32; ++j) word |= ((v[j] >> i) & 1u) << j;
+    F[(long long)i * nwords + w] = word;
+  }
+}
+
+// Single table: one thread per word.
+template <int EB>
+__global__ __launch_bounds__(256) void k_bitslice(const void* S, int n, int m, uint32_t* F, int nwords) {
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w < nwords) bitslice_words<EB>(S, n, m, F, nwords, w);
+}
+
+// Batched: blockIdx.y selects the job, threads stride over its words.
+__global__ __launch_bounds__(256) void k_bitslice_jobs(const JobDesc* jobs) {
+  const JobDesc jd = jobs[blockIdx.y];
+  for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < jd.nwords; w += gridDim.x * blockDim.x) {
+    uint32_t* F = const_cast<uint32_t*>(jd.F);
+    if (jd.s_elem_bytes == 1) bitslice_words<1>(jd.S, jd.n, jd.m, F, jd.nwords, w);
+    else if (jd.s_elem_bytes == 2) bitslice_words<2>(jd.S, jd.n, jd.m, F, jd.nwords, w);
+    else bitslice_words<4>(jd.S, jd.n, jd.m, F, jd.nwords, w);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Per-call initialisation: queue counters, NL start value 2^(n-1),
+// maxabs[0] = 2^n, and the b = 0 row / column of a requested spectrum.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_init_jobs(const JobDesc* jobs, JobDesc job0, int njobs,
+                                                   int* queue, int nqueue, int layout) {
+  const int j = blockIdx.x;
+  if (j >= njobs) return;
+  const JobDesc jd = jobs ? jobs[j] : job0;
+  if (j == 0) {
+    for (int i = threadIdx.x; i < nqueue; i += blockDim.x) queue[i] = 0;
+  }
+  if (threadIdx.x == 0) {
+    *jd.nl = 1 << (jd.n - 1);
+    if (jd.maxabs) jd.maxabs[0] = 1 << jd.n;
+  }
+  if (jd.spec) {
+    const long long N = 1LL << jd.n;
+    for (long long a = threadIdx.x; a < N; a += blockDim.x) {
+      const int v = (a == 0) ? (int)N : 0;
+      if (layout == 1) jd.spec[a] = v;
+      else jd.spec[a << jd.m] = v;
+    }
+  }
+}
+
+// Zero `count` ints (queue counters, per-batch maxima) without a memset node.
+__global__ __launch_bounds__(256) void k_zero(int* p, long long count) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < count;
+       i += (long long)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// n > 16, second pass: transform over the block index bits [bit0, bit0+R)
+// of T[slot][blk][a_lo] (in place), or, on the last pass, fold the maximum
+// and write the requested spectrum.
+// ---------------------------------------------------------------------------
+template <int R, bool LAST>
+__global__ __launch_bounds__(256) void k_combine(int32_t* T, long long kcount, int nblk_log, int bit0,
+                                                 int* slotmax, int32_t* spec, int layout, int m,
+                                                 long long kbase, long long mend) {
+  const int L = nblk_log;
+  const long long per_slot = (1LL << 16) << (L - R);  // threads per slot
+  const long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  const long long slot = idx / per_slot;
+  int mx = 0;
+  if (slot < kcount) {
+    const long long rem = idx - slot * per_slot;
+    const long long alo = rem & 0xFFFF;
+    const long long other = rem >> 16;  // block bits outside [bit0, bit0+R)
+    const long long lowmask = (1LL << bit0) - 1;
+    const long long base_blk = (other & lowmask) | ((other >> bit0) << (bit0 + R));
+    int32_t* base = T + (slot << (16 + L)) + alo;
+    int v[1 << R];
+#pragma unroll
+    for (int j = 0; j < (1 << R); ++j) v[j] = base[(base_blk | ((long long)j << bit0)) << 16];
+#pragma unroll
+    for (int h = 1; h < (1 << R); h <<= 1)
+#pragma unroll
+      for (int j = 0; j < (1 << R); ++j)
+        if (!(j & h)) {
+          const int a = v[j], c = v[j | h];
+          v[j] = a + c;
+          v[j | h] = a - c;
+        }
+    if constexpr (LAST) {
+      const long long k = kbase + slot;
+      const bool valid = k != 0 && k < mend;
+      const uint32_t b = (uint32_t)gray(k);
+#pragma unroll
+      for (int j = 0; j < (1 << R); ++j) {
+        mx = max(mx, v[j] < 0 ? -v[j] : v[j]);
+        if (spec && valid) {
+          const long long a = alo | ((base_blk | ((long long)j << bit0)) << 16);
+          if (layout == 1) spec[((long long)b << (16 + L)) | a] = -2 * v[j];
+          else spec[(a << m) | b] = -2 * v[j];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < (1 << R); ++j) base[(base_blk | ((long long)j << bit0)) << 16] = v[j];
+    }
+  }
+  if constexpr (LAST) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) mx = max(mx, __shfl_xor(mx, o, 64));
+    if ((threadIdx.x & 63) == 0 && slot < kcount) atomicMax(&slotmax[slot], mx);
+  }
+}
+
+// n > 16: per-mask maxima of the batch -> maxabs and NL.
+__global__ __launch_bounds__(256) void k_finalize_batch(const int* slotmax, long long kcount, long long kbase,
+                                                        long long mend, int n, int32_t* maxabs, int32_t* nl) {
+  const long long s = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  int cand = 0x7fffffff;
+  if (s < kcount) {
+    const long long k = kbase + s;
+    if (k != 0 && k < mend) {
+      const int mx = slotmax[s];
+      if (maxabs) maxabs[gray(k)] = 2 * mx;
+      cand = (1 << (n - 1)) - mx;
+    }
+  }
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) cand = min(cand, __shfl_xor(cand, o, 64));
+  if ((threadIdx.x & 63) == 0 && cand != 0x7fffffff) atomicMin(nl, cand);
+}
+
+}  // namespace sbw

@@ -1,0 +1,96 @@
+"""The C-ABI library: it loads, exports every symbol include/sbox_walsh.h
+declares, and rejects invalid arguments on the host before touching the GPU
+(no compute call is made here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1912_03732_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sbox_walsh.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(sbox_[a-z_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(B.LIB_PATH):
+        pytest.fail("libsboxwalsh.so not built: run __graft_entry__.build()")
+    return B.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(B.EXPORTS)
+
+
+def test_version(lib):
+    assert re.match(r"^\d+\.\d+\.\d+$", B.sbox_version())
+
+
+@pytest.mark.parametrize("n,m,layout,ok", [
+    (1, 1, 0, True), (16, 16, 0, True), (24, 16, 0, True), (16, 24, 0, True),
+    (0, 4, 0, False), (4, 0, 0, False), (25, 1, 0, False), (20, 21, 0, False),
+    (16, 16, 1, True), (16, 18, 2, True), (20, 16, 1, False), (4, 4, 3, False), (4, 4, -1, False)])
+def test_workspace_query(lib, n, m, layout, ok):
+    v = B.sbox_walsh_nl_workspace_bytes(n, m, layout)
+    assert (v > 0) == ok
+    if ok and n <= 16:
+        # queue counters + m bit-sliced slices of 2^(n-5) words
+        assert v >= 256 + m * (1 << max(0, n - 5)) * 4
+
+
+def test_large_n_workspace_grows_with_n(lib):
+    assert B.sbox_walsh_nl_workspace_bytes(20, 16, 0) > B.sbox_walsh_nl_workspace_bytes(17, 16, 0) > 0
+
+
+@pytest.mark.parametrize("args,status", [
+    (dict(n=0, m=4), B.SBOX_ERR_UNSUPPORTED),
+    (dict(n=4, m=25), B.SBOX_ERR_UNSUPPORTED),
+    (dict(S=0), B.SBOX_ERR_INVALID_ARG),
+    (dict(nl=0), B.SBOX_ERR_INVALID_ARG),
+    (dict(eb=3), B.SBOX_ERR_INVALID_ARG),
+    (dict(layout=5), B.SBOX_ERR_INVALID_ARG),
+    (dict(layout=1, spec=0), B.SBOX_ERR_INVALID_ARG),
+    (dict(ws=0), B.SBOX_ERR_WORKSPACE),
+    (dict(ws_bytes=16), B.SBOX_ERR_WORKSPACE),
+    (dict(ws=4096 + 8), B.SBOX_ERR_INVALID_ARG),
+    (dict(n=12, tuning=B.sbox_tuning(5, 0, 0, 0)), B.SBOX_ERR_INVALID_ARG),
+    (dict(n=16, tuning=B.sbox_tuning(7, 0, 0, 0)), B.SBOX_ERR_INVALID_ARG),
+    (dict(tuning=B.sbox_tuning(0, -1, 0, 0)), B.SBOX_ERR_INVALID_ARG),
+])
+def test_invalid_arguments_rejected_before_launch(lib, args, status):
+    # Fake (never dereferenced) pointers: validation rejects before any HIP call.
+    a = dict(S=4096, n=8, m=8, eb=1, mx=0, nl=8192, spec=0, layout=0, ws=4096, ws_bytes=1 << 20,
+             tuning=None)
+    a.update(args)
+    st = B.sbox_walsh_nl_ex(a["S"], a["n"], a["m"], a["eb"], a["mx"], a["nl"], a["spec"], a["layout"],
+                            a["ws"], a["ws_bytes"], a["tuning"], 0)
+    assert st == status
+    assert B.sbox_last_error() != ""
+
+
+def test_batched_rejects_large_n_and_bad_jobs(lib):
+    jobs = (B.sbox_job * 2)()
+    jobs[0].S, jobs[0].n, jobs[0].m, jobs[0].s_elem_bytes, jobs[0].nl = 4096, 17, 4, 1, 8192
+    assert B.sbox_walsh_nl_batched(jobs, 1, 4096, 1 << 20, 0) == B.SBOX_ERR_UNSUPPORTED
+    jobs[0].n, jobs[0].s_elem_bytes = 8, 3
+    assert B.sbox_walsh_nl_batched(jobs, 1, 4096, 1 << 20, 0) == B.SBOX_ERR_INVALID_ARG
+    jobs[0].s_elem_bytes, jobs[0].nl = 1, None
+    assert B.sbox_walsh_nl_batched(jobs, 1, 4096, 1 << 20, 0) == B.SBOX_ERR_INVALID_ARG
+    assert B.sbox_walsh_nl_batched(jobs, -1, 4096, 1 << 20, 0) == B.SBOX_ERR_INVALID_ARG
+    assert B.sbox_plan_launch(None, 0) == B.SBOX_ERR_INVALID_ARG
+    st, h = B.sbox_plan_create(jobs, 1, None)
+    assert st == B.SBOX_ERR_INVALID_ARG and not h
+    B.sbox_plan_destroy(None)  # no-op

@@ -1,0 +1,194 @@
+"""GPU parity: the HIP path against the CPU oracle, bit-exact (every output is
+an integer).  Sizes span several tiles and ragged tails; the full-size
+workloads are checked whole where the oracle finishes in seconds and on
+sampled masks (plus size-independent properties) where it does not."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1912_03732_amd import binding as B
+from paper_1912_03732_amd import inputs
+from tests.gpu_util import check_against_oracle, dev_table, first_diff, gpu_nl, table
+
+pytestmark = pytest.mark.gpu
+
+NT = min(16, os.cpu_count() or 1)
+
+
+@pytest.mark.parametrize("n", list(range(1, 17)))
+@pytest.mark.parametrize("m", [1, 3, 8])
+def test_fused_nl_all_n(n, m):
+    S = table(n, m, 1000 + 37 * n + m)
+    check_against_oracle(S, n, m, nthreads=NT)
+
+
+@pytest.mark.parametrize("n,m", [(5, 11), (6, 12), (9, 10), (12, 12), (13, 9), (14, 10), (15, 7), (16, 10)])
+def test_fused_nl_more_masks(n, m):
+    S = table(n, m, 2000 + n * m)
+    check_against_oracle(S, n, m, nthreads=NT)
+
+
+@pytest.mark.parametrize("n,p", [(9, 6), (9, 7), (9, 8), (10, 7), (10, 8), (11, 7), (11, 8), (12, 7), (12, 8),
+                                 (13, 8), (14, 8)])
+def test_every_register_split(n, p):
+    m = 9
+    S = table(n, m, 3000 + n * 10 + p)
+    check_against_oracle(S, n, m, nthreads=NT, tuning=B.sbox_tuning(p, 0, 0, 0))
+
+
+@pytest.mark.parametrize("chunk,grid", [(1, 1), (3, 7), (64, 2), (5, 0)])
+def test_chunk_and_grid_do_not_change_results(chunk, grid):
+    S = table(12, 11, 4000 + chunk)
+    check_against_oracle(S, 12, 11, nthreads=NT, tuning=B.sbox_tuning(0, chunk, grid, 0))
+
+
+@pytest.mark.parametrize("n,m", [(1, 1), (3, 2), (4, 6), (5, 5), (6, 3), (7, 7), (8, 8), (9, 5), (10, 6),
+                                 (11, 4), (12, 6), (13, 3), (14, 4), (15, 2), (16, 3)])
+@pytest.mark.parametrize("layout", [1, 2])
+def test_spectrum_layouts(n, m, layout):
+    S = table(n, m, 5000 + n * m)
+    nl, mx, spec = gpu_nl(S, n, m, spectrum="b" if layout == 1 else "a")
+    ref = oracle.spectrum(S, n, m, oracle.B_MAJOR if layout == 1 else oracle.A_MAJOR)
+    assert np.array_equal(spec, ref)
+    onl, omx = oracle.walsh_nl(S, n, m)
+    assert nl == onl and np.array_equal(mx, omx)
+
+
+def test_constant_component_extreme_values():
+    """A box whose top output bit is constant has |W(0, b)| = 2^n for those
+    masks; at n = 16 that is the one value the packed 16-bit path wraps."""
+    n = m = 16
+    S = (inputs.permutation(16, inputs.rng(6001)).astype(np.uint32) & 0x7FFF).astype(np.uint16)
+    nl, mx = check_against_oracle(S, n, m, nthreads=NT)
+    assert nl == 0 and mx[0x8000] == 65536
+    nl2, mx2, spec = gpu_nl(S[:1 << 12] & 0x7FF, 12, 12, spectrum="b")
+    assert np.array_equal(spec, oracle.spectrum(S[:1 << 12] & 0x7FF, 12, 12, oracle.B_MAJOR))
+
+
+def test_affine_and_constant_boxes():
+    for n, m in [(6, 6), (10, 10), (16, 4)]:
+        x = np.arange(1 << n, dtype=np.uint32)
+        S = ((x * 5) ^ (x >> 1)) & ((1 << m) - 1)  # linear over GF(2) after masking
+        check_against_oracle(S.astype(np.uint32), n, m, nthreads=NT)
+        check_against_oracle(np.zeros(1 << n, np.uint8), n, m, nthreads=NT)
+
+
+# ------------------------------------------------------------ workloads ---
+
+def test_workload_8x8():
+    w = inputs.workload_8x8()
+    for key in ("perm", "inv"):
+        S = w[key]
+        for layout in ("b", "a"):
+            nl, mx, spec = gpu_nl(S, 8, 8, spectrum=layout)
+            ref = oracle.spectrum(S, 8, 8, oracle.B_MAJOR if layout == "b" else oracle.A_MAJOR)
+            assert np.array_equal(spec, ref)
+        assert nl == oracle.walsh_nl(S, 8, 8)[0]
+    assert gpu_nl(w["inv"], 8, 8)[0] == 112
+    assert gpu_nl(inputs.aes_sbox(), 8, 8)[0] == 112
+
+
+def test_workload_16x16_inversion_closed_form():
+    w = inputs.workload_16x16()
+    nl, mx, _ = gpu_nl(w["inv"], 16, 16)
+    assert nl == 32512
+    assert int(mx[1:].max()) == 512
+
+
+@pytest.mark.slow
+def test_workload_16x16_permutation_full():
+    w = inputs.workload_16x16()
+    check_against_oracle(w["perm"], 16, 16, nthreads=NT)
+
+
+def test_workload_16x20_sampled():
+    w = inputs.workload_nonsquare()
+    S = w["s16x20"]
+    nl, mx, _ = gpu_nl(S, 16, 20)
+    assert mx.shape == (1 << 20,) and mx[0] == 1 << 16
+    g = inputs.rng(7001)
+    masks = np.unique(np.concatenate([g.integers(1, 1 << 20, size=200), [1, (1 << 20) - 1, 1 << 19]]))
+    assert np.array_equal(mx[masks], oracle.maxabs_for_masks(S, 16, 20, masks, nthreads=NT))
+    # the NL is the minimum over the per-mask values (any size)
+    assert nl == (1 << 15) - int(mx[1:].max()) // 2
+    assert np.all(mx[1:] % 2 == 0) and int(mx[1:].min()) > 0
+
+
+def test_workload_20x16_sampled():
+    w = inputs.workload_nonsquare()
+    S = w["s20x16"]
+    nl, mx, _ = gpu_nl(S, 20, 16)
+    g = inputs.rng(7002)
+    masks = np.unique(np.concatenate([g.integers(1, 1 << 16, size=24), [1, 0xFFFF, 0x8000]]))
+    assert np.array_equal(mx[masks], oracle.maxabs_for_masks(S, 20, 16, masks, nthreads=NT))
+    assert nl == (1 << 19) - int(mx[1:].max()) // 2
+
+
+def test_workload_12x12_slice_both_layouts():
+    S = inputs.workload_nonsquare()["slice12"]
+    for layout in ("a", "b"):
+        nl, mx, spec = gpu_nl(S, 12, 12, spectrum=layout)
+        ref = oracle.spectrum(S, 12, 12, oracle.A_MAJOR if layout == "a" else oracle.B_MAJOR)
+        assert np.array_equal(spec, ref)
+        assert nl == oracle.nl_from_spectrum(ref, 12, 12, oracle.A_MAJOR if layout == "a" else oracle.B_MAJOR)[0]
+
+
+@pytest.mark.parametrize("n,m", [(17, 3), (18, 5), (19, 2), (20, 4), (17, 7)])
+def test_large_n_full(n, m):
+    S = table(n, m, 8000 + n * m)
+    check_against_oracle(S, n, m, nthreads=NT)
+
+
+@pytest.mark.parametrize("n,m,layout", [(17, 2, "b"), (18, 3, "a")])
+def test_large_n_spectrum(n, m, layout):
+    S = table(n, m, 8100 + n * m)
+    nl, mx, spec = gpu_nl(S, n, m, spectrum=layout)
+    ref = oracle.spectrum(S, n, m, oracle.B_MAJOR if layout == "b" else oracle.A_MAJOR)
+    assert np.array_equal(spec, ref)
+
+
+def test_large_n_small_workspace_many_passes():
+    n, m = 17, 6
+    S = table(n, m, 8200)
+    need = B.sbox_walsh_nl_workspace_bytes(n, m, 0)
+    one_pass = 256 + 6 * (1 << 12) * 4 + 256 + 256 + (1 << 17) * 4 * 3  # room for three masks
+    ws = B.Workspace(one_pass)
+    assert one_pass < need
+    check_against_oracle(S, n, m, nthreads=NT, workspace=ws)
+
+
+def test_short_form_entry_point():
+    import torch
+    S = table(10, 9, 9000)
+    t = dev_table(S, 9)
+    mx = torch.empty(1 << 9, dtype=torch.int32, device="cuda")
+    nl = torch.empty(1, dtype=torch.int32, device="cuda")
+    st = B.sbox_walsh_nl(t.data_ptr(), 10, 9, mx.data_ptr(), nl.data_ptr(),
+                         int(torch.cuda.current_stream().cuda_stream))
+    assert st == B.SBOX_OK
+    torch.cuda.synchronize()
+    onl, omx = oracle.walsh_nl(S, 10, 9)
+    assert int(nl.item()) == onl and np.array_equal(mx.cpu().numpy(), omx)
+
+
+def test_element_width_and_high_bits():
+    import torch
+    n, m = 11, 7
+    S = table(n, m, 9100).astype(np.uint32)
+    junk = S | (np.arange(1 << n, dtype=np.uint32) << 7)
+    for dt in (torch.uint8, torch.uint16, torch.uint32):
+        info = np.iinfo({torch.uint8: np.uint8, torch.uint16: np.uint16, torch.uint32: np.uint32}[dt])
+        t = torch.from_numpy((junk & info.max).astype(info.dtype)).cuda()
+        nl, mx, _ = B.walsh_nl(t, n, m)
+        onl, omx = oracle.walsh_nl(S, n, m)
+        assert nl == onl and np.array_equal(mx.cpu().numpy(), omx)
+
+
+def test_repeated_calls_are_deterministic():
+    S = table(13, 10, 9200)
+    t = dev_table(S, 10)
+    ref = B.walsh_nl(t, 13, 10)[1].cpu().numpy()
+    for _ in range(5):
+        assert np.array_equal(B.walsh_nl(t, 13, 10)[1].cpu().numpy(), ref)
