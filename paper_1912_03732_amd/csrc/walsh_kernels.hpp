@@ -168,8 +168,17 @@ __device__ __forceinline__ void load_words(uint32_t (&G)[NW], const uint32_t* p,
 // ---------------------------------------------------------------------------
 // Main fused kernel, n <= 16 (MODE kBlock: one 2^16 block of a larger n).
 // ---------------------------------------------------------------------------
+constexpr int kLdsStride = kWG + 1;  // padded LDS row (odd number of words)
+
+// Workgroups per CU the register budget is tuned for: the 16-bit-input
+// kernel with the two-round exchange fits two (<= 256 VGPRs per lane).
 template <int N, int P_, int MODE>
-__global__ __launch_bounds__(kWG) void k_walsh(const KParams kp) {
+constexpr int min_blocks() {
+  return (N == 16 && P_ == 8 && MODE == kMax) ? 2 : 1;
+}
+
+template <int N, int P_, int MODE>
+__global__ __launch_bounds__(kWG, (min_blocks<N, P_, MODE>())) void k_walsh(const KParams kp) {
   constexpr int P = (N <= 8) ? N : P_;
   constexpr int Q = N - P;
   static_assert(Q >= 0 && Q <= P, "bad split");
@@ -181,7 +190,9 @@ __global__ __launch_bounds__(kWG) void k_walsh(const KParams kp) {
   constexpr int SWZ_SHIFT = (Q >= 1 && Q <= P - 1) ? (P - 1 - Q) : 0;
   constexpr int U2 = (Q >= 1 && Q <= P - 1) ? (1 << (P - 1 - Q)) : 1;
 
-  __shared__ uint32_t lds[(Q > 0) ? NR * kWG : 1];
+  constexpr bool TWO_ROUND = (MODE == kMax && Q == P && P == 8);
+  constexpr int LDS_WORDS = (Q == 0) ? 1 : (Q <= P - 1) ? NR * kWG : (TWO_ROUND ? 64 : NR) * kLdsStride;
+  __shared__ uint32_t lds[LDS_WORDS];
   __shared__ int red[kWG / 64];
   __shared__ long long s_item;
 
@@ -319,11 +330,12 @@ __global__ __launch_bounds__(kWG) void k_walsh(const KParams kp) {
         } else {
 #pragma unroll
           for (int d = 4; d <= LAST1; ++d) stage_regs<NR>(R, 1 << d);
-          // ---- LDS transpose: row u (low output pair), column = thread
-#pragma unroll
-          for (int u = 0; u < NR; ++u) lds[u * kWG + (tid ^ ((u >> SWZ_SHIFT) & 31))] = R[u];
-          __syncthreads();
           if constexpr (Q <= P - 1) {
+            // ---- LDS transpose: row u (low output pair), column = thread,
+            // columns XOR-swizzled by the reader's group-thread index
+#pragma unroll
+            for (int u = 0; u < NR; ++u) lds[u * kWG + (tid ^ ((u >> SWZ_SHIFT) & 31))] = R[u];
+            __syncthreads();
             // thread (g, v): pairs u = v*U2 + j, all 2^Q high inputs
 #pragma unroll
             for (int j = 0; j < U2; ++j) {
@@ -364,9 +376,45 @@ __global__ __launch_bounds__(kWG) void k_walsh(const KParams kp) {
             const int h = (tg >> 5) & 1;
             constexpr int HALF = 1 << (Q - 1);
             constexpr int H2 = 1 << (Q - 2);
+            if constexpr (TWO_ROUND) {
+              // Two half-size rounds (64 KiB of LDS, two workgroups per CU).
+              // Round r moves the elements (u, x_hi) with u[6] ^ x_hi[6] == r.
+              // A writer (x_hi = tid) frees register half r ^ tid[6] and the
+              // reader fills that same half with its i[6] == r ^ u[6] inputs,
+              // so physical register j holds logical input j ^ (flip << 6).
+              // The butterfly on bit 6 undoes the relabelling up to the sign
+              // of one half, which the maximum does not see.
+              const int wb6 = (tid >> 6) & 1;  // wave-uniform
+              const int ru = u >> 6;           // wave-uniform
 #pragma unroll
-            for (int i = 0; i < HALF; ++i)
-              R[i] = lds[u * kWG + (((g << Q) + h * HALF + i) ^ (u & 31))];
+              for (int r = 0; r < 2; ++r) {
+                if ((r ^ wb6) == 0) {
+#pragma unroll
+                  for (int j = 0; j < 64; ++j) lds[j * kLdsStride + tid] = R[j];
+                } else {
+#pragma unroll
+                  for (int j = 0; j < 64; ++j) lds[j * kLdsStride + tid] = R[64 + j];
+                }
+                __syncthreads();
+                const int src = (u & 63) * kLdsStride + h * HALF + ((r ^ ru) << 6);
+                if ((r ^ wb6) == 0) {
+#pragma unroll
+                  for (int i = 0; i < 64; ++i) R[i] = lds[src + i];
+                } else {
+#pragma unroll
+                  for (int i = 0; i < 64; ++i) R[64 + i] = lds[src + i];
+                }
+                if (r == 0) __syncthreads();
+              }
+            } else {
+              // one round, rows padded to an odd stride: conflict-free both ways
+#pragma unroll
+              for (int u2 = 0; u2 < NR; ++u2) lds[u2 * kLdsStride + tid] = R[u2];
+              __syncthreads();
+              const int src = u * kLdsStride + (g << Q) + h * HALF;
+#pragma unroll
+              for (int i = 0; i < HALF; ++i) R[i] = lds[src + i];
+            }
 #pragma unroll
             for (int d = 0; d < Q - 1; ++d) stage_regs<NR>(R, 1 << d);
 #pragma unroll
