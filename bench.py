@@ -37,6 +37,8 @@ def parse():
                     help="masks of the 16x16 box the CPU oracle is timed on")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--batched", action="store_true", help="also time the mixed 4096-box batch")
+    ap.add_argument("--serving", action="store_true", help="also run the Poisson serving rate sweep")
+    ap.add_argument("--serving-count", type=int, default=5000, help="requests per rate in the sweep")
     return ap.parse_args()
 
 
@@ -142,6 +144,9 @@ def main():
     }
     if args.batched:
         out["batched"] = bench_batched(torch, B, inputs, dev)
+    if args.serving:
+        from paper_1912_03732_amd import serving
+        out["serving"] = serving.sweep(count=args.serving_count)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(S_host, n, m, args.cpu_sample_masks)
     print(json.dumps(out), flush=True)

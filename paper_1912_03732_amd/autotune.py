@@ -1,0 +1,205 @@
+"""Autotuner for the launch parameters of the fused Walsh/NL kernels.
+
+For one (n, m) it sweeps the register split (split_p: bits of x a thread
+transforms before the LDS exchange), the chunk (consecutive Gray-code masks
+per thread group per work item) and the persistent grid size, times each
+candidate with HIP events on a seeded random box, and keeps the fastest one
+whose per-mask maxima and NL are bit-identical to the default launch's.  The
+choice is cached in a JSON file keyed by GPU architecture, library version
+and (n, m); ``lookup`` is consulted by ``binding.walsh_nl`` when no tuning is
+passed.  Batched plans are tuned over the chunk only (the split follows n).
+"""
+from __future__ import annotations
+
+import json
+import os
+import threading
+from typing import Dict, List, Optional, Tuple
+
+CACHE_ENV = "SBOX_TUNING_CACHE"
+_lock = threading.Lock()
+_cache: Optional[Dict] = None
+_cache_path: Optional[str] = None
+
+
+def cache_path() -> str:
+    p = os.environ.get(CACHE_ENV)
+    if p:
+        return p
+    return os.path.join(os.path.expanduser("~"), ".cache", "sboxwalsh", "tuning.json")
+
+
+def valid_splits(n: int) -> List[int]:
+    """Register splits compiled for the max-only kernel of size n."""
+    if n <= 8:
+        return [n]
+    return [p for p in (6, 7, 8) if 1 <= n - p <= p]
+
+
+def candidates(n: int, m: int, cus: int = 256) -> List[Tuple[int, int, int]]:
+    """(split_p, chunk, grid) triples; grid 0 means 'fill every CU'."""
+    out = []
+    chunks = [1, 2, 4, 8, 16, 32, 64]
+    grids = [0] if n >= 13 else [0, cus, 2 * cus]
+    for p in valid_splits(n):
+        for c in chunks:
+            for g in grids:
+                out.append((p if n > 8 else 0, c, g))
+    return out
+
+
+def key(arch: str, version: str, n: int, m: int) -> str:
+    return "%s|%s|n%d|m%d" % (arch, version, n, m)
+
+
+def _load() -> Dict:
+    global _cache, _cache_path
+    path = cache_path()
+    if _cache is None or _cache_path != path:
+        try:
+            with open(path) as f:
+                _cache = json.load(f)
+        except (OSError, ValueError):
+            _cache = {}
+        _cache_path = path
+    return _cache
+
+
+def store(k: str, value: Dict) -> None:
+    with _lock:
+        c = _load()
+        c[k] = value
+        path = cache_path()
+        os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+        tmp = path + ".tmp%d" % os.getpid()
+        with open(tmp, "w") as f:
+            json.dump(c, f, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+
+
+def get(k: str) -> Optional[Dict]:
+    with _lock:
+        return _load().get(k)
+
+
+def _arch_and_version() -> Tuple[str, str]:
+    import torch
+
+    from . import binding as B
+    props = torch.cuda.get_device_properties(torch.cuda.current_device())
+    arch = getattr(props, "gcnArchName", "unknown").split(":")[0]
+    return arch, B.sbox_version()
+
+
+def lookup(n: int, m: int):
+    """Cached best tuning for (n, m) on this device, or None."""
+    try:
+        arch, ver = _arch_and_version()
+    except Exception:
+        return None
+    v = get(key(arch, ver, n, m))
+    if not v:
+        return None
+    from . import binding as B
+    return B.sbox_tuning(int(v["split_p"]), int(v["chunk"]), int(v["grid"]), 0)
+
+
+def _time(fn, reps: int) -> float:
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(s)
+    for _ in range(reps):
+        fn()
+    b.record(s)
+    b.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def tune(n: int, m: int, reps: int = 3, seed: int = 191203732, save: bool = True,
+         max_candidates: Optional[int] = None) -> Dict:
+    """Sweep the candidates for (n, m); return {'best': {...}, 'results': [...]}."""
+    import torch
+
+    from . import binding as B
+    from . import inputs
+    g = inputs.rng(seed + 7919 * n + m)
+    table = inputs.permutation(n, g) if n == m else inputs.random_function(n, m, g)
+    S = B.table_to_device(table, m)
+    ws = B.Workspace(B.sbox_walsh_nl_workspace_bytes(n, m, 0))
+    nl = torch.empty(1, dtype=torch.int32, device=S.device)
+    mx = torch.empty(1 << m, dtype=torch.int32, device=S.device)
+    stream = int(torch.cuda.current_stream().cuda_stream)
+
+    def run(t):
+        st = B.sbox_walsh_nl_ex(S.data_ptr(), n, m, S.element_size(), mx.data_ptr(), nl.data_ptr(), 0, 0,
+                                ws.ptr, ws.nbytes, t, stream)
+        if st != B.SBOX_OK:
+            raise B.SboxError(st, B.last_error())
+
+    run(None)
+    torch.cuda.synchronize()
+    ref_mx = mx.clone()
+    ref_nl = int(nl.item())
+    cus = torch.cuda.get_device_properties(S.device).multi_processor_count
+    results = []
+    cands = candidates(n, m, cus)
+    if max_candidates:
+        cands = cands[:max_candidates]
+    for (p, c, gr) in cands:
+        t = B.sbox_tuning(p, c, gr, 0)
+        try:
+            ms = _time(lambda: run(t), reps)
+        except B.SboxError as e:
+            results.append({"split_p": p, "chunk": c, "grid": gr, "ms": None, "exact": False, "error": str(e)})
+            continue
+        exact = bool(torch.equal(mx, ref_mx)) and int(nl.item()) == ref_nl
+        results.append({"split_p": p, "chunk": c, "grid": gr, "ms": ms, "exact": exact})
+    ok = [r for r in results if r["exact"] and r["ms"] is not None]
+    best = min(ok, key=lambda r: r["ms"]) if ok else None
+    if best and save:
+        arch, ver = _arch_and_version()
+        store(key(arch, ver, n, m), {k: best[k] for k in ("split_p", "chunk", "grid", "ms")})
+    return {"best": best, "results": results}
+
+
+def tune_batched(tables, ns, ms, reps: int = 3, chunks=(1, 2, 4, 8, 16, 32, 64), save: bool = True) -> Dict:
+    """Pick the chunk for a batched plan over these boxes (bit-exact vs the default)."""
+    import torch
+
+    from . import binding as B
+    base = B.Plan(tables, ns, ms)
+    base.launch()
+    torch.cuda.synchronize()
+    ref_nl = base.nl.clone()
+    ref_mx = [x.clone() for x in base.maxabs]
+    base.close()
+    results = []
+    for c in chunks:
+        plan = B.Plan(tables, ns, ms, tuning=B.sbox_tuning(0, c, 0, 0))
+        t = _time(plan.launch, reps)
+        exact = bool(torch.equal(plan.nl, ref_nl)) and all(torch.equal(a, b) for a, b in zip(plan.maxabs, ref_mx))
+        results.append({"chunk": c, "ms": t, "exact": exact})
+        plan.close()
+    ok = [r for r in results if r["exact"]]
+    best = min(ok, key=lambda r: r["ms"]) if ok else None
+    if best and save:
+        arch, ver = _arch_and_version()
+        sig = "batch%d" % len(tables)
+        store("%s|%s|%s" % (arch, ver, sig), best)
+    return {"best": best, "results": results}
+
+
+if __name__ == "__main__":
+    import argparse
+    ap = argparse.ArgumentParser(description="tune the fused Walsh/NL launch for given sizes")
+    ap.add_argument("sizes", nargs="+", help="n x m pairs such as 16x16 12x12")
+    ap.add_argument("--reps", type=int, default=3)
+    a = ap.parse_args()
+    for s in a.sizes:
+        n, m = (int(v) for v in s.lower().split("x"))
+        r = tune(n, m, reps=a.reps)
+        print(s, json.dumps(r["best"]))

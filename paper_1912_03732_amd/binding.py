@@ -212,6 +212,9 @@ def walsh_nl(S, n: int, m: int, *, spectrum: Optional[str] = None, maxabs: bool 
     if layout != SPECTRUM_NONE:
         shape = (1 << m, 1 << n) if layout == SPECTRUM_B_MAJOR else (1 << n, 1 << m)
         spec = torch.empty(shape, dtype=torch.int32, device=dev)
+    if tuning is None and layout == SPECTRUM_NONE:
+        from . import autotune
+        tuning = autotune.lookup(n, m)
     need = sbox_walsh_nl_workspace_bytes(n, m, layout)
     if need == 0:
         raise SboxError(SBOX_ERR_UNSUPPORTED, "unsupported n=%d m=%d layout=%d" % (n, m, layout))
