@@ -39,7 +39,26 @@ def parse():
     ap.add_argument("--batched", action="store_true", help="also time the mixed 4096-box batch")
     ap.add_argument("--serving", action="store_true", help="also run the Poisson serving rate sweep")
     ap.add_argument("--serving-count", type=int, default=5000, help="requests per rate in the sweep")
+    ap.add_argument("--extra", action="store_true",
+                    help="also time the other workloads (8x8, 20x16, 16x20, 12x12 slice, 16x16 spectrum)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (reference for HBM byte counters) and exit")
     return ap.parse_args()
+
+
+def measured_traffic():
+    """HBM bytes per dispatch of the fused 16x16 kernel from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE runs, or None if the kernel source has
+    changed since they were taken."""
+    import hashlib
+    try:
+        with open(os.path.join(ROOT, "profiles", "k_walsh_16x16_traffic.json")) as f:
+            rec = json.load(f)
+        with open(os.path.join(ROOT, "paper_1912_03732_amd", "csrc", "walsh_kernels.hpp"), "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()[:16]
+    except (OSError, ValueError):
+        return None
+    return rec["traffic_bytes_per_dispatch"] if rec.get("kernel_source_sha256_16") == sha else None
 
 
 def host_cores() -> int:
@@ -80,6 +99,9 @@ def main():
     from paper_1912_03732_amd import binding as B
     from paper_1912_03732_amd import inputs
 
+    if args.copy_calibration:
+        copy_calibration(torch)
+        return
     n = m = 16
     w = inputs.workload_16x16()
     S_host = w["perm"]
@@ -137,19 +159,85 @@ def main():
                                "max|W| per mask + NL, no spectrum" % (inputs.SEED_BASE + 2),
                    "n": n, "m": m, "masks": (1 << m) - 1, "nl": nl_val},
         "roofline": {"bound": "alu", "achieved": achieved_tops, "peak": PEAK_PK16_TOPS, "unit": "TOP/s",
-                     "frac": achieved_tops / PEAK_PK16_TOPS, "traffic": None,
+                     "frac": achieved_tops / PEAK_PK16_TOPS, "traffic": measured_traffic(),
                      "kernel": "k_walsh<16,8,0>", "kernel_ms": ev_mean,
                      "int32_valu_peak": PEAK_INT32_TOPS,
                      "int32_valu_frac": achieved_tops / PEAK_INT32_TOPS},
     }
     if args.batched:
         out["batched"] = bench_batched(torch, B, inputs, dev)
+    if args.extra:
+        out["extra"] = bench_extra(torch, B, inputs, dev)
     if args.serving:
         from paper_1912_03732_amd import serving
         out["serving"] = serving.sweep(count=args.serving_count)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(S_host, n, m, args.cpu_sample_masks)
     print(json.dumps(out), flush=True)
+
+
+def copy_calibration(torch, nbytes=1 << 30, reps=3):
+    """A plain device-to-device copy of known size: the reference that scales
+    the FETCH_SIZE / WRITE_SIZE counters into bytes."""
+    src = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes, "reps": reps}), flush=True)
+
+
+def _time_call(torch, fn, reps):
+    fn()
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(s)
+    for _ in range(reps):
+        fn()
+    b.record(s)
+    b.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def bench_extra(torch, B, inputs, dev):
+    """The other workloads, timed with HIP events (ms per call)."""
+    out = {}
+
+    def single(S_host, n, m, layout=0, reps=5):
+        S = B.table_to_device(S_host, m, device=dev)
+        nl = torch.empty(1, dtype=torch.int32, device=dev)
+        mx = torch.empty(1 << m, dtype=torch.int32, device=dev)
+        spec = torch.empty(1 << (n + m), dtype=torch.int32, device=dev) if layout else None
+        ws = B.Workspace(B.sbox_walsh_nl_workspace_bytes(n, m, layout), dev)
+        sptr = int(torch.cuda.current_stream(dev).cuda_stream)
+
+        def call():
+            st = B.sbox_walsh_nl_ex(S.data_ptr(), n, m, S.element_size(), mx.data_ptr(), nl.data_ptr(),
+                                    spec.data_ptr() if spec is not None else 0, layout, ws.ptr, ws.nbytes,
+                                    None, sptr)
+            if st != 0:
+                raise RuntimeError(B.last_error())
+        ms = _time_call(torch, call, reps)
+        coeffs = (1 << n) * ((1 << m) - 1)
+        row = {"ms": ms, "coeff_per_s": coeffs / (ms * 1e-3), "int_ops_per_s": n * coeffs / (ms * 1e-3),
+               "nl": int(nl.item())}
+        if layout:
+            row["spectrum_GB_per_s"] = 4 * (1 << (n + m)) / (ms * 1e-3) / 1e9
+        return row
+
+    w8 = inputs.workload_8x8()
+    out["8x8_perm_fused"] = single(w8["perm"], 8, 8, reps=50)
+    out["8x8_perm_spectrum_b"] = single(w8["perm"], 8, 8, 1, reps=50)
+    out["8x8_perm_spectrum_a"] = single(w8["perm"], 8, 8, 2, reps=50)
+    ns = inputs.workload_nonsquare()
+    out["16x20_fused"] = single(ns["s16x20"], 16, 20, reps=2)
+    out["20x16_fused"] = single(ns["s20x16"], 20, 16, reps=1)
+    out["12x12_slice_spectrum_a"] = single(ns["slice12"], 12, 12, 2, reps=10)
+    out["12x12_slice_spectrum_b"] = single(ns["slice12"], 12, 12, 1, reps=10)
+    out["16x16_perm_spectrum_b"] = single(inputs.workload_16x16()["perm"], 16, 16, 1, reps=2)
+    return out
 
 
 def bench_batched(torch, B, inputs, dev, reps=5):
