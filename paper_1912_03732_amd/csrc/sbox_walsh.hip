@@ -177,6 +177,13 @@ long long large_batch_for(int n, int m, size_t bytes) {
   return std::min(b, M);
 }
 
+// 17 <= n <= 20 without a spectrum: the recompute kernel k_walsh_big.
+constexpr int kBigMaxGrid = 1024;
+bool use_big(int n, int layout) { return n > 16 && n <= 20 && layout == 0; }
+size_t big_fixed_bytes(int n, int m) { return kQueueBytes + f_bytes(n, m); }
+size_t big_per_wg_bytes(int n) { return (size_t)4 << (n - 5); }
+size_t big_bytes(int n, int m) { return big_fixed_bytes(n, m) + kBigMaxGrid * big_per_wg_bytes(n); }
+
 long long default_large_batch(int n, int m) {
   const long long b = std::max(1LL, (1LL << 26) >> n);
   return std::min(b, 1LL << m);
@@ -200,6 +207,51 @@ void pick_chunk(long long masks_total, int groups, int grid_cap, int chunk_req, 
   *chunk = (int)c;
 }
 
+// --------------------------------------------- 17 <= n <= 20, max only ----
+template <int L>
+const void* big_kernel() { return (const void*)&k_walsh_big<L>; }
+
+sbox_status run_big(const void* S, int n, int m, int eb, int32_t* maxabs, int32_t* nl, void* ws, size_t ws_bytes,
+                    const sbox_tuning* tun, hipStream_t st, int* queue) {
+  int cus = 0;
+  sbox_status s = device_info(&cus);
+  if (s) return s;
+  const int L = n - 16;
+  const int nwords = 1 << (n - 5);
+  uint32_t* FT = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(ws) + kQueueBytes);
+  uint32_t* gbuf = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(ws) + big_fixed_bytes(n, m));
+  {
+    const void* S_ = S;
+    int L_ = L, m_ = m, nw_ = nwords;
+    void* args[] = {(void*)&S_, &L_, &m_, &FT, &nw_};
+    const void* fn = eb == 1 ? (const void*)&k_bitslice_big<1> : eb == 2 ? (const void*)&k_bitslice_big<2>
+                                                                         : (const void*)&k_bitslice_big<4>;
+    s = launch(fn, dim3((nwords + 255) / 256), dim3(256), args, st);
+    if (s) return s;
+  }
+  const void* fn = L == 1 ? big_kernel<1>() : L == 2 ? big_kernel<2>() : L == 3 ? big_kernel<3>() : big_kernel<4>();
+  int occ = 1;
+  s = occupancy(fn, &occ);
+  if (s) return s;
+  const long long M = 1LL << m;
+  long long grid = (tun && tun->grid) ? tun->grid : (long long)occ * cus;
+  grid = std::min<long long>(grid, kBigMaxGrid);
+  grid = std::min<long long>(grid, (long long)((ws_bytes - big_fixed_bytes(n, m)) / big_per_wg_bytes(n)));
+  int chunk = (tun && tun->chunk) ? tun->chunk : (int)std::max(1LL, std::min(16LL, M / (grid * 16)));
+  BigParams bp{};
+  bp.FT = FT;
+  bp.gbuf = gbuf;
+  bp.maxabs = maxabs;
+  bp.nl = nl;
+  bp.queue = queue;
+  bp.total_items = (M + chunk - 1) / chunk;
+  bp.m = m;
+  bp.chunk = chunk;
+  grid = std::min<long long>(grid, bp.total_items);
+  void* args[] = {&bp};
+  return launch(fn, dim3((unsigned)grid), dim3(kWG), args, st);
+}
+
 // ------------------------------------------------------- one S-box call ----
 sbox_status run_single(const void* S, int n, int m, int eb, int32_t* maxabs, int32_t* nl, int32_t* spec,
                        int layout, void* ws, size_t ws_bytes, const sbox_tuning* tun, hipStream_t st) {
@@ -210,6 +262,20 @@ sbox_status run_single(const void* S, int n, int m, int eb, int32_t* maxabs, int
   uint32_t* F = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(ws) + kQueueBytes);
   const int nwords = n >= 5 ? 1 << (n - 5) : 1;
 
+  if (use_big(n, layout)) {
+    // init (NL, maxabs[0], queue), then the x_hi-inner bit-slicing and the kernel
+    JobDesc jd{};
+    jd.maxabs = maxabs;
+    jd.nl = nl;
+    jd.n = n;
+    jd.m = m;
+    const JobDesc* nulljobs = nullptr;
+    int one = 1, nq = 64, lay = 0;
+    void* args[] = {(void*)&nulljobs, &jd, &one, &queue, &nq, &lay};
+    s = launch((const void*)&k_init_jobs, dim3(1), dim3(256), args, st);
+    if (s) return s;
+    return run_big(S, n, m, eb, maxabs, nl, ws, ws_bytes, tun, st, queue);
+  }
   // bit-sliced component words
   {
     const void* S_ = S;
@@ -535,6 +601,7 @@ size_t sbox_walsh_nl_workspace_bytes(int n, int m, int layout) {
   if (layout < 0 || layout > 2) return 0;
   if (layout != 0 && n + m > 34) return 0;
   if (n <= 16) return kQueueBytes + f_bytes(n, m);
+  if (use_big(n, layout)) return big_bytes(n, m);
   return large_bytes(n, m, default_large_batch(n, m));
 }
 
@@ -562,7 +629,11 @@ sbox_status sbox_walsh_nl_ex(const void* S, int n, int m, int s_elem_bytes, int3
   if (reinterpret_cast<uintptr_t>(workspace) & 255) return fail(SBOX_ERR_INVALID_ARG, "workspace not 256-byte aligned");
   if (n <= 16 && workspace_bytes < need)
     return fail(SBOX_ERR_WORKSPACE, "workspace of %zu bytes, need %zu", workspace_bytes, need);
-  if (n > 16 && large_batch_for(n, m, workspace_bytes) < 1)
+  if (use_big(n, layout)) {
+    if (workspace_bytes < big_fixed_bytes(n, m) + big_per_wg_bytes(n))
+      return fail(SBOX_ERR_WORKSPACE, "workspace of %zu bytes too small for n=%d (need >= %zu)", workspace_bytes, n,
+                  big_fixed_bytes(n, m) + big_per_wg_bytes(n));
+  } else if (n > 16 && large_batch_for(n, m, workspace_bytes) < 1)
     return fail(SBOX_ERR_WORKSPACE, "workspace of %zu bytes too small for n=%d (need >= %zu)", workspace_bytes, n,
                 large_bytes(n, m, 1));
   return run_single(S, n, m, s_elem_bytes, maxabs_per_b, nl, spectrum, layout, workspace, workspace_bytes,

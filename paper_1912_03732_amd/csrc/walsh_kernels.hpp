@@ -474,6 +474,197 @@ __global__ __launch_bounds__(kWG, (min_blocks<N, P_, MODE>())) void k_walsh(cons
 }
 
 // ---------------------------------------------------------------------------
+// n = 16 + L, 1 <= L <= 4, max mode: recompute instead of materialising.
+//
+// Write x = (x_hi : L bits, x_lo : 16 bits).  For a fixed high output index
+// a_hi the coefficients W(a_hi, a_lo) form one 2^16-point transform over
+// x_lo whose inputs already sum over x_hi.  The table is bit-sliced so that
+// a word holds the 2^L high inputs and 2^B (B = 5 - L) low inputs of one
+// group of x_lo; the popcount stages then cover x_hi and the B low bits at
+// once, and for a fixed a_hi each word yields 2^B outputs.  A task
+// (mask b, a_hi) is thus a 2^16-point job of the same shape as the n = 16
+// kernel: 3 + L register stages, the two-round LDS exchange, and 8 stages
+// with the lane swap.  Values reach 2^(7+L) before the exchange (int16) and
+// up to 2^(15+L) at the end, so the last L + 1 stages run in int32, a chunk
+// of registers at a time.  A workgroup walks its masks in Gray-code order,
+// keeping the mask's words G_b in a private global buffer (L2-resident,
+// 2^(n-3) bytes) that each task streams back in.
+// ---------------------------------------------------------------------------
+struct BigParams {
+  const uint32_t* FT;   // [m][2^(n-5)] words in the x_hi-inner layout
+  uint32_t* gbuf;       // [grid][2^(n-5)] per-workgroup words of the current mask
+  int32_t* maxabs;
+  int32_t* nl;
+  int* queue;
+  long long total_items;
+  int m;
+  int chunk;
+};
+
+template <int L>
+__global__ __launch_bounds__(kWG, 2) void k_walsh_big(const BigParams bp) {
+  constexpr int N = 16 + L;
+  constexpr int B = 5 - L;                 // low bits of x_lo inside a word
+  constexpr int KB = 8 - B;                // word-group bits per thread
+  constexpr int NWT = 1 << KB;             // words per thread
+  constexpr int NR = 128;                  // packed registers
+  constexpr int OPW = 1 << B;              // outputs per word for one a_hi
+  constexpr int K16 = 7 - L;               // phase-2 stages still in int16
+  constexpr int NK = 1 << (7 - K16);       // packed registers per int32 chunk
+  static_assert(L >= 1 && L <= 4, "n = 17..20");
+  constexpr long long NWORDS = 1LL << (N - 5);
+
+  __shared__ uint32_t lds[64 * kLdsStride];
+  __shared__ int red[kWG / 64];
+  __shared__ long long s_item;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  uint32_t* gb = bp.gbuf + (long long)blockIdx.x * NWORDS;
+  const long long wbase = (long long)tid * NWT;  // this thread's words
+  const long long kend = 1LL << bp.m;
+
+  for (;;) {
+    if (tid == 0) s_item = (long long)atomicAdd(bp.queue, 1);
+    __syncthreads();
+    const long long item = s_item;
+    __syncthreads();
+    if (item >= bp.total_items) break;
+    const long long kfirst = item * bp.chunk;
+    int runmin = 0x7fffffff;
+
+    for (int step = 0; step < bp.chunk; ++step) {
+      const long long k = kfirst + step;
+      const bool inrange = k < kend;
+      // ---- words of mask gray(k) into the private buffer (own words only)
+      if (inrange) {
+        if (step == 0) {
+          const long long gk = gray(k);
+#pragma unroll 1
+          for (int c = 0; c < NWT; c += 4) {
+            uint4 acc = make_uint4(0, 0, 0, 0);
+            for (int i = 0; i < bp.m; ++i)
+              if ((gk >> i) & 1) {
+                const uint4 v = *reinterpret_cast<const uint4*>(bp.FT + (long long)i * NWORDS + wbase + c);
+                acc.x ^= v.x; acc.y ^= v.y; acc.z ^= v.z; acc.w ^= v.w;
+              }
+            *reinterpret_cast<uint4*>(gb + wbase + c) = acc;
+          }
+        } else {
+          const int i = __builtin_ctzll((unsigned long long)k);
+#pragma unroll 4
+          for (int c = 0; c < NWT; c += 4) {
+            uint4 acc = *reinterpret_cast<const uint4*>(gb + wbase + c);
+            const uint4 v = *reinterpret_cast<const uint4*>(bp.FT + (long long)i * NWORDS + wbase + c);
+            acc.x ^= v.x; acc.y ^= v.y; acc.z ^= v.z; acc.w ^= v.w;
+            *reinterpret_cast<uint4*>(gb + wbase + c) = acc;
+          }
+        }
+      }
+      const bool valid = inrange && k != 0;
+      int maskmax = 0;
+
+      for (int ahi = 0; ahi < (1 << L); ++ahi) {
+        // ---- phase 1: popcount stages over (x_hi, B low bits), then KB - 1 register stages
+        uint32_t R[NR];
+        const uint32_t lhi = walsh_mask(ahi << B);
+#pragma unroll
+        for (int c = 0; c < NWT; c += 4) {
+          const uint4 v = inrange ? *reinterpret_cast<const uint4*>(gb + wbase + c) : make_uint4(0, 0, 0, 0);
+          const uint32_t g4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const uint32_t G = g4[q] ^ lhi;
+#pragma unroll
+            for (int a = 0; a < OPW / 2; ++a) {
+              const int c0 = __builtin_popcount(G ^ walsh_mask(a)) - 16;
+              const int c1 = __builtin_popcount(G ^ walsh_mask(a | (OPW / 2))) - 16;
+              R[((c + q) * (OPW / 2)) + a] = __builtin_amdgcn_perm((uint32_t)c1, (uint32_t)c0, 0x05040100u);
+            }
+          }
+        }
+#pragma unroll
+        for (int d = B - 1; d < 7; ++d) stage_regs<NR>(R, 1 << d);
+
+        // ---- two-round LDS exchange (as in the n = 16 kernel)
+        const int u = (tid & 31) | ((tid >> 6) << 5);
+        const int h = (tid >> 5) & 1;
+        const int wb6 = (tid >> 6) & 1;
+        const int ru = u >> 6;
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+          if ((r ^ wb6) == 0) {
+#pragma unroll
+            for (int j = 0; j < 64; ++j) lds[j * kLdsStride + tid] = R[j];
+          } else {
+#pragma unroll
+            for (int j = 0; j < 64; ++j) lds[j * kLdsStride + tid] = R[64 + j];
+          }
+          __syncthreads();
+          const int src = (u & 63) * kLdsStride + h * 128 + ((r ^ ru) << 6);
+          if ((r ^ wb6) == 0) {
+#pragma unroll
+            for (int i = 0; i < 64; ++i) R[i] = lds[src + i];
+          } else {
+#pragma unroll
+            for (int i = 0; i < 64; ++i) R[64 + i] = lds[src + i];
+          }
+          if (r == 0) __syncthreads();
+        }
+        // ---- phase 2: K16 packed stages, then int32 chunks: stages, lane swap, last stage
+#pragma unroll
+        for (int d = 0; d < K16; ++d) stage_regs<NR>(R, 1 << d);
+        int hiv = -0x7fffffff, lov = 0x7fffffff;
+#pragma unroll
+        for (int c = 0; c < (1 << K16); ++c) {
+          int lo[NK], hi[NK];
+#pragma unroll
+          for (int kk = 0; kk < NK; ++kk) {
+            const uint32_t v = R[c + (kk << K16)];
+            lo[kk] = unpack_lo(v);
+            hi[kk] = unpack_hi(v);
+          }
+#pragma unroll
+          for (int hb = 1; hb < NK; hb <<= 1)
+#pragma unroll
+            for (int kk = 0; kk < NK; ++kk) {
+              if (kk & hb) continue;
+              const int a0 = lo[kk], a1 = lo[kk | hb];
+              lo[kk] = a0 + a1; lo[kk | hb] = a0 - a1;
+              const int b0 = hi[kk], b1 = hi[kk | hb];
+              hi[kk] = b0 + b1; hi[kk | hb] = b0 - b1;
+            }
+#pragma unroll
+          for (int kk = 0; kk < NK / 2; ++kk) {
+            uint32_t x0 = (uint32_t)lo[kk], x1 = (uint32_t)lo[kk + NK / 2];
+            swap_halves(x0, x1);
+            uint32_t y0 = (uint32_t)hi[kk], y1 = (uint32_t)hi[kk + NK / 2];
+            swap_halves(y0, y1);
+            const int s0 = (int)x0 + (int)x1, d0 = (int)x0 - (int)x1;
+            const int s1 = (int)y0 + (int)y1, d1 = (int)y0 - (int)y1;
+            hiv = max(hiv, max(max(s0, d0), max(s1, d1)));
+            lov = min(lov, min(min(s0, d0), min(s1, d1)));
+          }
+        }
+        int mx = max(hiv, -lov);
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) mx = max(mx, __shfl_xor(mx, o, 64));
+        if (lane == 0) red[tid >> 6] = mx;
+        __syncthreads();
+        mx = max(max(red[0], red[1]), max(red[2], red[3]));
+        maskmax = max(maskmax, mx);
+        __syncthreads();  // red and lds are rewritten by the next task
+      }
+      if (tid == 0 && valid) {
+        if (bp.maxabs) bp.maxabs[gray(k)] = 2 * maskmax;
+        runmin = min(runmin, (1 << (N - 1)) - maskmax);
+      }
+    }
+    if (tid == 0 && runmin != 0x7fffffff) atomicMin(bp.nl, runmin);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Bit-slicing: F[i][w] = bit i of S[32w + j] at bit j (j < min(32, 2^n)).
 // ---------------------------------------------------------------------------
 template <int EB>
@@ -502,6 +693,28 @@ template <int EB>
 __global__ __launch_bounds__(256) void k_bitslice(const void* S, int n, int m, uint32_t* F, int nwords) {
   const int w = blockIdx.x * blockDim.x + threadIdx.x;
   if (w < nwords) bitslice_words<EB>(S, n, m, F, nwords, w);
+}
+
+// Bit-slicing for k_walsh_big: word w = x_lo >> B holds, at bit
+// j = x_lo_low + 2^B * x_hi, bit i of S[x_hi * 2^16 + x_lo].
+template <int EB>
+__global__ __launch_bounds__(256) void k_bitslice_big(const void* S, int L, int m, uint32_t* FT, int nwords) {
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= nwords) return;
+  const int B = 5 - L;
+  uint32_t v[32];
+#pragma unroll
+  for (int j = 0; j < 32; ++j) {
+    const long long xlo = ((long long)w << B) | (j & ((1 << B) - 1));
+    const long long xhi = j >> B;
+    v[j] = load_entry<EB>(S, (xhi << 16) | xlo);
+  }
+  for (int i = 0; i < m; ++i) {
+    uint32_t word = 0;
+#pragma unroll
+    for (int j = 0; j < 32; ++j) word |= ((v[j] >> i) & 1u) << j;
+    FT[(long long)i * nwords + w] = word;
+  }
 }
 
 // Batched: blockIdx.y selects the job, threads stride over its words.

@@ -135,7 +135,7 @@ def test_workload_12x12_slice_both_layouts():
         assert nl == oracle.nl_from_spectrum(ref, 12, 12, oracle.A_MAJOR if layout == "a" else oracle.B_MAJOR)[0]
 
 
-@pytest.mark.parametrize("n,m", [(17, 3), (18, 5), (19, 2), (20, 4), (17, 7)])
+@pytest.mark.parametrize("n,m", [(17, 3), (18, 5), (19, 2), (20, 4), (17, 7), (21, 2), (22, 1)])
 def test_large_n_full(n, m):
     S = table(n, m, 8000 + n * m)
     check_against_oracle(S, n, m, nthreads=NT)
@@ -149,14 +149,34 @@ def test_large_n_spectrum(n, m, layout):
     assert np.array_equal(spec, ref)
 
 
-def test_large_n_small_workspace_many_passes():
+def test_large_n_small_workspace_few_workgroups():
+    """n = 17..20: a workspace below the query limits the number of
+    persistent workgroups (each keeps its mask's words in its own slot)."""
     n, m = 17, 6
     S = table(n, m, 8200)
     need = B.sbox_walsh_nl_workspace_bytes(n, m, 0)
-    one_pass = 256 + 6 * (1 << 12) * 4 + 256 + 256 + (1 << 17) * 4 * 3  # room for three masks
-    ws = B.Workspace(one_pass)
-    assert one_pass < need
+    small = 256 + 6 * (1 << 12) * 4 + 3 * (1 << 12) * 4  # three workgroup slots
+    ws = B.Workspace(small)
+    assert small < need
     check_against_oracle(S, n, m, nthreads=NT, workspace=ws)
+
+
+def test_large_n_small_workspace_many_passes():
+    """n > 20: the block path processes as many masks per pass as the
+    workspace holds."""
+    n, m = 21, 3
+    S = table(n, m, 8201)
+    need = B.sbox_walsh_nl_workspace_bytes(n, m, 0)
+    two = 256 + ((3 * (1 << 16) * 4 + 255) // 256) * 256 + 256 + 256 + (1 << 21) * 4 * 2  # two masks
+    ws = B.Workspace(two)
+    assert two < need
+    check_against_oracle(S, n, m, nthreads=NT, workspace=ws)
+
+
+@pytest.mark.parametrize("n,m,chunk,grid", [(18, 9, 1, 3), (19, 8, 5, 0), (20, 6, 2, 100)])
+def test_large_n_tuning(n, m, chunk, grid):
+    S = table(n, m, 8300 + n + m)
+    check_against_oracle(S, n, m, nthreads=NT, tuning=B.sbox_tuning(0, chunk, grid, 0))
 
 
 def test_short_form_entry_point():
