@@ -234,12 +234,13 @@ __global__ __launch_bounds__(kWG, (min_blocks<N, P_, MODE>())) void k_walsh(cons
     const long long wb = (MODE == kBlock ? ((long long)xblk << 11) : 0) + (long long)tg * NW;
     const int n = jd.n;
     int runmin = 0x7fffffff;
-    uint32_t G[NW];
+    uint32_t G[NW], Fn[NW];
 
     for (int step = 0; step < C; ++step) {
       const long long k = kfirst + step;
       const bool inrange = k < kend;
-      // ---- component words of mask gray(k) (Gray-code walk)
+      // ---- component words of mask gray(k) (Gray-code walk); the slice for
+      // the next mask is fetched one mask ahead to hide its L2 latency
       if (step == 0) {
 #pragma unroll
         for (int w = 0; w < NW; ++w) G[w] = 0;
@@ -249,8 +250,12 @@ __global__ __launch_bounds__(kWG, (min_blocks<N, P_, MODE>())) void k_walsh(cons
             if ((gk >> i) & 1) load_words<NW>(G, jd.F + (long long)i * jd.nwords + wb, true);
         }
       } else if (inrange) {
-        const int i = __builtin_ctzll((unsigned long long)k);
-        load_words<NW>(G, jd.F + (long long)i * jd.nwords + wb, true);
+#pragma unroll
+        for (int w = 0; w < NW; ++w) G[w] ^= Fn[w];
+      }
+      if (step + 1 < C && k + 1 < kend) {
+        const int i = __builtin_ctzll((unsigned long long)(k + 1));
+        load_words<NW>(Fn, jd.F + (long long)i * jd.nwords + wb, false);
       }
       const bool valid = inrange && k != 0;
       const uint32_t b = (uint32_t)gray(k);
