@@ -237,6 +237,22 @@ def bench_extra(torch, B, inputs, dev):
     out["12x12_slice_spectrum_a"] = single(ns["slice12"], 12, 12, 2, reps=10)
     out["12x12_slice_spectrum_b"] = single(ns["slice12"], 12, 12, 1, reps=10)
     out["16x16_perm_spectrum_b"] = single(inputs.workload_16x16()["perm"], 16, 16, 1, reps=2)
+    # component criteria (balancedness, correlation immunity, autocorrelation): two
+    # transforms per mask in LDS
+    for n in (8, 12, 14):
+        S = B.table_to_device(inputs.permutation(n, inputs.rng(inputs.SEED_BASE + 6)), n, device=dev)
+        summ = torch.empty(8, dtype=torch.int32, device=dev)
+        sptr = int(torch.cuda.current_stream(dev).cuda_stream)
+
+        def crit():
+            st = B.sbox_criteria(S.data_ptr(), n, n, S.element_size(), summ.data_ptr(), 0, 0, 0, 0, sptr)
+            if st != 0:
+                raise RuntimeError(B.last_error())
+        ms = _time_call(torch, crit, 3 if n == 14 else 10)
+        coeffs = (1 << n) * ((1 << n) - 1)
+        out["criteria_%dx%d" % (n, n)] = {"ms": ms, "coeff_per_s": coeffs / (ms * 1e-3),
+                                          "int_ops_per_s": 2 * n * coeffs / (ms * 1e-3),
+                                          "summary": summ.cpu().tolist()[:6]}
     return out
 
 

@@ -160,6 +160,31 @@ sbox_status sbox_plan_create(const sbox_job* jobs, int32_t count, const sbox_tun
 sbox_status sbox_plan_launch(const sbox_plan* plan, void* stream);
 void sbox_plan_destroy(sbox_plan* plan);
 
+/*
+ * Further criteria of the component functions (the paper's future work,
+ * Section 7), computed from the same transforms for every nonzero mask b:
+ *   balancedness         W(0, b) == 0;
+ *   correlation immunity order t: W(a, b) == 0 for all 1 <= wt(a) <= t,
+ *                        resiliency order = t when every component is balanced;
+ *   autocorrelation      r_b(d) = sum_x (-1)^(b.S(x) XOR b.S(x XOR d)), obtained
+ *                        as 2^-n times the transform of W(., b)^2 (Wiener-Khinchin);
+ *   absolute indicator   max_{b != 0, d != 0} |r_b(d)|;
+ *   propagation order k: r_b(d) == 0 for all 1 <= wt(d) <= k.
+ *   summary      device int32[8] (required): {NL, number of unbalanced masks,
+ *                correlation-immunity order, resiliency order (-1 if some
+ *                component is unbalanced), absolute indicator, propagation
+ *                order, 0, 0}.
+ *   w0_per_b, minwt_per_b, acmax_per_b, pcwt_per_b  device int32[2^m] or NULL:
+ *                W(0,b); min wt(a) over a != 0 with W(a,b) != 0 (n + 1 if none);
+ *                max_{d != 0} |r_b(d)|; min wt(d) over d != 0 with r_b(d) != 0
+ *                (n + 1 if none).  Entry b = 0 is written as 0.
+ * Limits: 1 <= n <= 14, 1 <= m <= 24 (each mask's transform stays in LDS).
+ * No workspace, no allocation, no host synchronisation.
+ */
+sbox_status sbox_criteria(const void* S, int n, int m, int s_elem_bytes, int32_t* summary,
+                          int32_t* w0_per_b, int32_t* minwt_per_b, int32_t* acmax_per_b,
+                          int32_t* pcwt_per_b, void* stream);
+
 /* Text describing the last non-OK status returned on this thread ("" if none). */
 const char* sbox_last_error(void);
 

@@ -58,6 +58,11 @@ def _load():
         lib.oracle_walsh_column.argtypes = [u32p, ctypes.c_int, ctypes.c_int, ctypes.c_uint32, i32p]
         lib.oracle_walsh_entry.argtypes = [u32p, ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32]
         lib.oracle_walsh_entry.restype = ctypes.c_int32
+        lib.oracle_criteria.argtypes = [u32p, ctypes.c_int, ctypes.c_int, i32p, i32p, i32p, i32p, i32p,
+                                        ctypes.c_int]
+        lib.oracle_criteria.restype = ctypes.c_int
+        lib.oracle_autocorrelation.argtypes = [u32p, ctypes.c_int, ctypes.c_int, ctypes.c_uint32, i32p]
+        lib.oracle_autocorrelation.restype = ctypes.c_int
         for f in (lib.oracle_walsh_nl, lib.oracle_walsh_maxabs_masks, lib.oracle_spectrum,
                   lib.oracle_nl_from_spectrum, lib.oracle_walsh_column):
             f.restype = ctypes.c_int
@@ -142,3 +147,34 @@ def walsh_entry(S, n: int, a: int, b: int) -> int:
     lib = _load()
     t = _table(S, n)
     return int(lib.oracle_walsh_entry(_p(t, ctypes.c_uint32), n, int(a), int(b)))
+
+
+CRITERIA_FIELDS = ("nl", "unbalanced", "ci_order", "resiliency", "abs_indicator", "pc_order")
+
+
+def criteria(S, n: int, m: int, nthreads: int = 1):
+    """Component criteria (balancedness, correlation immunity, autocorrelation).
+
+    Returns (summary dict, per-mask dict of arrays w0, minwt, acmax, pcwt)."""
+    lib = _load()
+    t = _table(S, n)
+    M = 1 << m
+    arrs = {k: np.empty(M, dtype=np.int32) for k in ("w0", "minwt", "acmax", "pcwt")}
+    summ = np.zeros(8, dtype=np.int32)
+    rc = lib.oracle_criteria(_p(t, ctypes.c_uint32), n, m, _p(arrs["w0"], ctypes.c_int32),
+                             _p(arrs["minwt"], ctypes.c_int32), _p(arrs["acmax"], ctypes.c_int32),
+                             _p(arrs["pcwt"], ctypes.c_int32), _p(summ, ctypes.c_int32), int(nthreads))
+    if rc != 0:
+        raise ValueError("oracle_criteria rejected its arguments")
+    return {k: int(summ[i]) for i, k in enumerate(CRITERIA_FIELDS)}, arrs
+
+
+def autocorrelation(S, n: int, m: int, b: int) -> np.ndarray:
+    """r_b(d) for all d, summed from the definition."""
+    lib = _load()
+    t = _table(S, n)
+    r = np.empty(1 << n, dtype=np.int32)
+    rc = lib.oracle_autocorrelation(_p(t, ctypes.c_uint32), n, m, int(b), _p(r, ctypes.c_int32))
+    if rc != 0:
+        raise ValueError("oracle_autocorrelation rejected its arguments")
+    return r

@@ -223,3 +223,106 @@ int oracle_nl_from_spectrum(const int32_t* W, int n, int m, int layout, int32_t*
     *nl = best;
     return 0;
 }
+
+/*
+ * Further criteria of the component functions, the future work named in the
+ * paper's conclusion (Section 7), each from its textbook definition:
+ *   balancedness:        W(0, b) == 0 (the component b.S takes 0 and 1 equally often);
+ *   correlation immunity: order t if W(a, b) == 0 for every a with 1 <= wt(a) <= t;
+ *                         resiliency order = that t when also balanced, else -1;
+ *   autocorrelation:     r_b(d) = sum_x (-1)^(f_b(x) XOR f_b(x XOR d));
+ *   absolute indicator:  max over d != 0 of |r_b(d)|;
+ *   propagation order:   k if r_b(d) == 0 for every d with 1 <= wt(d) <= k.
+ * Aggregates take the worst case over nonzero masks b.  Per-mask outputs
+ * (each may be NULL, 2^m entries, entry 0 left as 0):
+ *   w0[b]     = W(0, b)
+ *   minwt[b]  = min wt(a) over a != 0 with W(a, b) != 0   (n + 1 if none)
+ *   acmax[b]  = max_{d != 0} |r_b(d)|
+ *   pcwt[b]   = min wt(d) over d != 0 with r_b(d) != 0   (n + 1 if none)
+ * summary[0..5] = {NL, #unbalanced masks, CI order, resiliency order,
+ *                  absolute indicator, propagation order}.
+ * The autocorrelation is summed directly from its definition (O(4^n) per mask).
+ */
+static int weight32(uint32_t v) {
+    int w = 0;
+    while (v) {
+        v &= v - 1u;
+        ++w;
+    }
+    return w;
+}
+
+int oracle_criteria(const uint32_t* S, int n, int m, int32_t* w0, int32_t* minwt, int32_t* acmax,
+                    int32_t* pcwt, int32_t* summary, int nthreads) {
+    if (!S || !summary || !valid_nm(n, m) || n > 16) return -1;
+    const uint32_t N = 1u << n;
+    const int64_t M = (int64_t)1 << m;
+    int32_t nl = (int32_t)(N >> 1), unbal = 0, ciw = n + 1, ac = 0, pcw = n + 1;
+    int failed = 0;
+    if (nthreads < 1) nthreads = 1;
+    if (w0) w0[0] = 0;
+    if (minwt) minwt[0] = 0;
+    if (acmax) acmax[0] = 0;
+    if (pcwt) pcwt[0] = 0;
+#pragma omp parallel num_threads(nthreads) reduction(min : nl, ciw, pcw) reduction(max : ac) \
+    reduction(+ : unbal) reduction(| : failed)
+    {
+        int32_t* f = (int32_t*)malloc(sizeof(int32_t) * N);
+        int8_t* g = (int8_t*)malloc(N);
+        if (!f || !g) {
+            failed = 1;
+        } else {
+#pragma omp for schedule(dynamic, 1)
+            for (int64_t b = 1; b < M; ++b) {
+                for (uint32_t x = 0; x < N; ++x) g[x] = (int8_t)parity32((uint32_t)b & S[x]);
+                polarity_column(S, n, (uint32_t)b, f);
+                fwht_inplace(f, n);
+                const int32_t mx = max_abs(f, N);
+                int mw = n + 1;
+                for (uint32_t a = 1; a < N; ++a)
+                    if (f[a] != 0 && weight32(a) < mw) mw = weight32(a);
+                int32_t amax = 0;
+                int pw = n + 1;
+                for (uint32_t d = 1; d < N; ++d) {
+                    int32_t r = 0;
+                    for (uint32_t x = 0; x < N; ++x) r += (g[x] ^ g[x ^ d]) ? -1 : 1;
+                    const int32_t ar = r < 0 ? -r : r;
+                    if (ar > amax) amax = ar;
+                    if (r != 0 && weight32(d) < pw) pw = weight32(d);
+                }
+                if (w0) w0[b] = f[0];
+                if (minwt) minwt[b] = mw;
+                if (acmax) acmax[b] = amax;
+                if (pcwt) pcwt[b] = pw;
+                const int32_t nlb = ((int32_t)N - mx) >> 1;
+                if (nlb < nl) nl = nlb;
+                if (f[0] != 0) unbal += 1;
+                if (mw < ciw) ciw = mw;
+                if (amax > ac) ac = amax;
+                if (pw < pcw) pcw = pw;
+            }
+        }
+        free(f);
+        free(g);
+    }
+    if (failed) return -1;
+    summary[0] = nl;
+    summary[1] = unbal;
+    summary[2] = ciw - 1;
+    summary[3] = unbal == 0 ? ciw - 1 : -1;
+    summary[4] = ac;
+    summary[5] = pcw - 1;
+    return 0;
+}
+
+/* Autocorrelation column r_b(d) for all d, from the definition. */
+int oracle_autocorrelation(const uint32_t* S, int n, int m, uint32_t b, int32_t* r) {
+    if (!S || !r || !valid_nm(n, m) || n > 16) return -1;
+    const uint32_t N = 1u << n;
+    for (uint32_t d = 0; d < N; ++d) {
+        int32_t acc = 0;
+        for (uint32_t x = 0; x < N; ++x) acc += (parity32(b & S[x]) ^ parity32(b & S[x ^ d])) ? -1 : 1;
+        r[d] = acc;
+    }
+    return 0;
+}

@@ -52,7 +52,7 @@ class sbox_job(ctypes.Structure):
 # Every exported symbol of include/sbox_walsh.h.
 EXPORTS = ("sbox_walsh_nl", "sbox_walsh_nl_ex", "sbox_walsh_nl_workspace_bytes",
            "sbox_walsh_nl_batched", "sbox_batched_workspace_bytes", "sbox_plan_create",
-           "sbox_plan_launch", "sbox_plan_destroy", "sbox_last_error", "sbox_version")
+           "sbox_plan_launch", "sbox_plan_destroy", "sbox_criteria", "sbox_last_error", "sbox_version")
 
 _lib = None
 
@@ -79,6 +79,8 @@ def load(path: str = LIB_PATH):
     lib.sbox_plan_launch.argtypes = [vp, vp]
     lib.sbox_plan_destroy.argtypes = [vp]
     lib.sbox_plan_destroy.restype = None
+    lib.sbox_criteria.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, vp, vp]
+    lib.sbox_criteria.restype = ctypes.c_int
     lib.sbox_last_error.restype = ctypes.c_char_p
     lib.sbox_version.restype = ctypes.c_char_p
     for f in ("sbox_walsh_nl", "sbox_walsh_nl_ex", "sbox_walsh_nl_batched", "sbox_plan_create",
@@ -136,6 +138,12 @@ def sbox_plan_launch(plan: int, stream: int) -> int:
 
 def sbox_plan_destroy(plan: int) -> None:
     load().sbox_plan_destroy(plan)
+
+
+def sbox_criteria(S: int, n: int, m: int, s_elem_bytes: int, summary: int, w0_per_b: int,
+                  minwt_per_b: int, acmax_per_b: int, pcwt_per_b: int, stream: int) -> int:
+    return load().sbox_criteria(S, n, m, s_elem_bytes, summary, w0_per_b, minwt_per_b, acmax_per_b,
+                                pcwt_per_b, stream)
 
 
 def sbox_last_error() -> str:
@@ -298,3 +306,26 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+CRITERIA_FIELDS = ("nl", "unbalanced", "ci_order", "resiliency", "abs_indicator", "pc_order")
+
+
+def criteria(S, n: int, m: int, *, per_mask: bool = True, stream=None):
+    """Balancedness, correlation immunity / resiliency and autocorrelation
+    criteria of every nonzero component (n <= 14).  Returns (summary dict,
+    dict of per-mask tensors w0, minwt, acmax, pcwt or None)."""
+    torch = _torch()
+    if not isinstance(S, torch.Tensor) or not S.is_cuda:
+        raise TypeError("S must be a device tensor")
+    S = S.contiguous()
+    dev = S.device
+    summ = torch.empty(8, dtype=torch.int32, device=dev)
+    arrs = {k: torch.empty(1 << m, dtype=torch.int32, device=dev) for k in ("w0", "minwt", "acmax", "pcwt")} \
+        if per_mask else None
+    ptr = (lambda k: arrs[k].data_ptr()) if arrs else (lambda k: 0)
+    _check(sbox_criteria(S.data_ptr(), n, m, S.element_size(), summ.data_ptr(), ptr("w0"), ptr("minwt"),
+                         ptr("acmax"), ptr("pcwt"), _stream(torch, stream)))
+    torch.cuda.synchronize(dev)
+    v = summ.cpu().tolist()
+    return {k: int(v[i]) for i, k in enumerate(CRITERIA_FIELDS)}, arrs

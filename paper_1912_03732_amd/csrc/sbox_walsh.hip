@@ -711,6 +711,48 @@ sbox_status sbox_walsh_nl_batched(const sbox_job* jobs, int32_t count, void* wor
   return launch_batch(L, workspace, st);
 }
 
+sbox_status sbox_criteria(const void* S, int n, int m, int s_elem_bytes, int32_t* summary, int32_t* w0_per_b,
+                          int32_t* minwt_per_b, int32_t* acmax_per_b, int32_t* pcwt_per_b, void* stream) {
+  if (n < 1 || n > 14 || m < 1 || m > 24)
+    return fail(SBOX_ERR_UNSUPPORTED, "criteria need 1<=n<=14 and 1<=m<=24 (n=%d m=%d)", n, m);
+  if (!S || !summary) return fail(SBOX_ERR_INVALID_ARG, "S or summary is null");
+  if (s_elem_bytes != 1 && s_elem_bytes != 2 && s_elem_bytes != 4)
+    return fail(SBOX_ERR_INVALID_ARG, "s_elem_bytes must be 1, 2 or 4 (got %d)", s_elem_bytes);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  int cus = 0;
+  sbox_status s = device_info(&cus);
+  if (s) return s;
+  {
+    int n_ = n;
+    void* args[] = {&summary, &n_, &w0_per_b, &minwt_per_b, &acmax_per_b, &pcwt_per_b};
+    s = launch((const void*)&k_criteria_init, dim3(1), dim3(64), args, st);
+    if (s) return s;
+  }
+  const void* fn = s_elem_bytes == 1 ? (const void*)&k_criteria<1>
+                 : s_elem_bytes == 2 ? (const void*)&k_criteria<2> : (const void*)&k_criteria<4>;
+  int occ = 1;
+  s = occupancy(fn, &occ);
+  if (s) return s;
+  CritParams cp{};
+  cp.S = S;
+  cp.eb = s_elem_bytes;
+  cp.n = n;
+  cp.m = m;
+  cp.crit = summary;
+  cp.w0 = w0_per_b;
+  cp.minwt = minwt_per_b;
+  cp.acmax = acmax_per_b;
+  cp.pcwt = pcwt_per_b;
+  const long long grid = std::min<long long>((1LL << m) - 1, (long long)occ * cus);
+  {
+    void* args[] = {&cp};
+    s = launch(fn, dim3((unsigned)std::max(1LL, grid)), dim3(256), args, st);
+    if (s) return s;
+  }
+  void* args[] = {&summary};
+  return launch((const void*)&k_criteria_finish, dim3(1), dim3(64), args, st);
+}
+
 struct sbox_plan {
   BatchLayout layout;
   void* dev = nullptr;

@@ -136,6 +136,14 @@ __device__ __forceinline__ void swap_halves(uint32_t& a, uint32_t& b) {
   b = r[1];
 }
 
+// An opaque copy: keeps the compiler from hoisting the per-thread output
+// addresses of the store modes out of the mask loop (hundreds of them,
+// which would otherwise be precomputed and spilled).
+__device__ __forceinline__ int opaque(int v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
 __device__ __forceinline__ int unpack_lo(uint32_t v) { return (int)(int16_t)(v & 0xFFFFu); }
 __device__ __forceinline__ int unpack_hi(uint32_t v) { return (int)v >> 16; }
 
@@ -358,7 +366,7 @@ __global__ __launch_bounds__(kWG, (min_blocks<N, P_, MODE>())) void k_walsh(cons
               for (int r = 0; r < NR; ++r) {
                 if (r & fb) continue;
                 const int j = r >> Q, y = r & ((1 << Q) - 1);
-                const int u = tg * U2 + j;
+                const int u = opaque(tg) * U2 + j;
                 const uint32_t uu = R[r], vv = R[r | fb];
                 emit(aidx(u, 0) | ((uint32_t)y << P), unpack_lo(uu) + unpack_lo(vv));
                 emit(aidx(u, 1) | ((uint32_t)y << P), unpack_hi(uu) + unpack_hi(vv));
@@ -425,15 +433,21 @@ __global__ __launch_bounds__(kWG, (min_blocks<N, P_, MODE>())) void k_walsh(cons
 #pragma unroll
             for (int i = 0; i < H2; ++i) swap_halves(R[i], R[i + H2]);
             if constexpr (STORE) {
+              // With the two-round exchange a wave whose physical register
+              // halves are swapped (flip = tid[6] ^ u[6]) ends with the
+              // lanes of h = 1 holding the negated outputs.
+              int sgn = 1;
+              if constexpr (TWO_ROUND) sgn = ((((tid >> 6) ^ (u >> 6)) & 1) && h) ? -1 : 1;
+              const uint32_t abase = (uint32_t)opaque((int)(aidx(u, 0) | ((uint32_t)(h * H2) << P)));
 #pragma unroll
               for (int i = 0; i < H2; ++i) {
                 const uint32_t uu = R[i], vv = R[i + H2];
-                const uint32_t ah = (uint32_t)(i + h * H2) << P;
-                const uint32_t top = 1u << (N - 1);
-                emit(aidx(u, 0) | ah, unpack_lo(uu) + unpack_lo(vv));
-                emit(aidx(u, 1) | ah, unpack_hi(uu) + unpack_hi(vv));
-                emit(aidx(u, 0) | ah | top, unpack_lo(uu) - unpack_lo(vv));
-                emit(aidx(u, 1) | ah | top, unpack_hi(uu) - unpack_hi(vv));
+                const uint32_t a0 = abase + ((uint32_t)i << P);
+                constexpr uint32_t top = 1u << (N - 1);
+                emit(a0, sgn * (unpack_lo(uu) + unpack_lo(vv)));
+                emit(a0 + 16, sgn * (unpack_hi(uu) + unpack_hi(vv)));
+                emit(a0 + top, sgn * (unpack_lo(uu) - unpack_lo(vv)));
+                emit(a0 + top + 16, sgn * (unpack_hi(uu) - unpack_hi(vv)));
               }
             } else {
               Tracker t; t.reset();
@@ -733,6 +747,130 @@ __global__ __launch_bounds__(256) void k_bitslice_jobs(const JobDesc* jobs) {
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// Component criteria (n <= 14): balancedness, correlation immunity and the
+// autocorrelation spectrum of every nonzero component.  One workgroup
+// transforms one mask at a time in LDS (int32, 2^n words):
+//   W = H f, then v(a) = (W(a)/2)^2 (int32, wrapping) and V = H v, where
+//   V(d) = 2^(n-2) r(d) exactly (Wiener-Khinchin), |V| <= 2^(2n-2) < 2^31,
+//   so the wrapping intermediate sums still give the exact V.
+// Per-mask results go to the optional arrays; aggregates use atomics into
+// crit[]: {NL, #unbalanced, min CI weight, -, abs indicator, min PC weight}.
+// ---------------------------------------------------------------------------
+struct CritParams {
+  const void* S;
+  int eb, n, m;
+  int32_t* crit;     // 8 ints
+  int32_t* w0;       // W(0, b)
+  int32_t* minwt;    // min wt(a), a != 0, W(a, b) != 0 (n + 1 if none)
+  int32_t* acmax;    // max_{d != 0} |r_b(d)|
+  int32_t* pcwt;     // min wt(d), d != 0, r_b(d) != 0 (n + 1 if none)
+};
+
+__device__ __forceinline__ void lds_fwht(int32_t* buf, int n) {
+  const int half = 1 << (n - 1);
+  for (int h = 1; h <= half; h <<= 1) {
+    for (int p = threadIdx.x; p < half; p += blockDim.x) {
+      const int i = ((p & ~(h - 1)) << 1) | (p & (h - 1));
+      const int32_t u = buf[i], v = buf[i + h];
+      buf[i] = (int32_t)((uint32_t)u + (uint32_t)v);
+      buf[i + h] = (int32_t)((uint32_t)u - (uint32_t)v);
+    }
+    __syncthreads();
+  }
+}
+
+template <bool IS_MAX>
+__device__ __forceinline__ int block_reduce(int v, int* red) {
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int w = __shfl_xor(v, o, 64);
+    v = IS_MAX ? max(v, w) : min(v, w);
+  }
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  int r = red[0];
+  for (int i = 1; i < (int)(blockDim.x >> 6); ++i) r = IS_MAX ? max(r, red[i]) : min(r, red[i]);
+  __syncthreads();
+  return r;
+}
+
+template <int EB>
+__global__ __launch_bounds__(256) void k_criteria(const CritParams p) {
+  __shared__ int32_t buf[1 << 14];
+  __shared__ int red[4];
+  const int n = p.n;
+  const int N = 1 << n;
+  const long long M = 1LL << p.m;
+  for (long long b = blockIdx.x + 1; b < M; b += gridDim.x) {
+    for (int x = threadIdx.x; x < N; x += blockDim.x)
+      buf[x] = (__builtin_popcount((uint32_t)b & load_entry<EB>(p.S, x)) & 1) ? -1 : 1;
+    __syncthreads();
+    lds_fwht(buf, n);
+    int mx = 0, mw = n + 1, w0 = 0;
+    for (int a = threadIdx.x; a < N; a += blockDim.x) {
+      const int v = buf[a];
+      mx = max(mx, v < 0 ? -v : v);
+      if (a == 0) w0 = v;
+      else if (v != 0) mw = min(mw, __builtin_popcount(a));
+      const int hv = v / 2;  // every W is even for n >= 1
+      buf[a] = (int32_t)((uint32_t)hv * (uint32_t)hv);
+    }
+    __syncthreads();
+    mx = block_reduce<true>(mx, red);
+    mw = block_reduce<false>(mw, red);
+    lds_fwht(buf, n);
+    int ac = 0, pw = n + 1;
+    for (int d = threadIdx.x; d < N; d += blockDim.x) {
+      if (d == 0) continue;
+      const int r = (int)((uint32_t)buf[d] << 2) >> n;  // 4 V(d) / 2^n, exact
+      ac = max(ac, r < 0 ? -r : r);
+      if (r != 0) pw = min(pw, __builtin_popcount(d));
+    }
+    ac = block_reduce<true>(ac, red);
+    pw = block_reduce<false>(pw, red);
+    if (threadIdx.x == 0) {
+      if (p.w0) p.w0[b] = w0;
+      if (p.minwt) p.minwt[b] = mw;
+      if (p.acmax) p.acmax[b] = ac;
+      if (p.pcwt) p.pcwt[b] = pw;
+      atomicMin(&p.crit[0], (N - mx) >> 1);
+      if (w0 != 0) atomicAdd(&p.crit[1], 1);
+      atomicMin(&p.crit[2], mw);
+      atomicMax(&p.crit[4], ac);
+      atomicMin(&p.crit[5], pw);
+    }
+    __syncthreads();
+  }
+}
+
+// crit[] start values; per-mask outputs at b = 0 are defined as 0.
+__global__ void k_criteria_init(int32_t* crit, int n, int32_t* w0, int32_t* minwt, int32_t* acmax, int32_t* pcwt) {
+  if (threadIdx.x == 0) {
+    crit[0] = 1 << (n - 1);
+    crit[1] = 0;
+    crit[2] = n + 1;
+    crit[3] = 0;
+    crit[4] = 0;
+    crit[5] = n + 1;
+    crit[6] = 0;
+    crit[7] = 0;
+    if (w0) w0[0] = 0;
+    if (minwt) minwt[0] = 0;
+    if (acmax) acmax[0] = 0;
+    if (pcwt) pcwt[0] = 0;
+  }
+}
+
+// Orders from the minimum weights: CI = minwt - 1, resiliency = CI if balanced.
+__global__ void k_criteria_finish(int32_t* crit) {
+  if (threadIdx.x == 0) {
+    crit[2] = crit[2] - 1;
+    crit[3] = crit[1] == 0 ? crit[2] : -1;
+    crit[5] = crit[5] - 1;
+  }
+}
 // ---------------------------------------------------------------------------
 // Per-call initialisation: queue counters, NL start value 2^(n-1),
 // maxabs[0] = 2^n, and the b = 0 row / column of a requested spectrum.
