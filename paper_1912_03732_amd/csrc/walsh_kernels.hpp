@@ -79,6 +79,7 @@ struct KParams {
 };
 
 typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(1))) int32_t gint32;  // global memory
 typedef int16_t s16x2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ uint32_t pk_add(uint32_t a, uint32_t b) {
@@ -205,7 +206,8 @@ __global__ __launch_bounds__(kWG, (min_blocks<N, P_, MODE>())) void k_walsh(cons
   __shared__ long long s_item;
 
   const int tid = threadIdx.x;
-  const int g = tid >> Q;                 // thread group in this workgroup
+  // thread group in this workgroup (wave-uniform when a group spans whole waves)
+  const int g = (Q >= 6) ? __builtin_amdgcn_readfirstlane(tid >> Q) : (tid >> Q);
   const int tg = tid & ((1 << Q) - 1);    // thread within the group
   const int lane = tid & 63;
   const int C = kp.chunk;
@@ -213,7 +215,8 @@ __global__ __launch_bounds__(kWG, (min_blocks<N, P_, MODE>())) void k_walsh(cons
   for (;;) {
     if (tid == 0) s_item = (long long)atomicAdd(kp.queue, 1);
     __syncthreads();
-    const long long item = s_item;
+    // the item is workgroup-uniform: keep it (and what derives from it) scalar
+    const long long item = __builtin_amdgcn_readfirstlane((int)s_item);
     __syncthreads();
     if (item >= kp.total_items) break;
 
@@ -270,23 +273,32 @@ __global__ __launch_bounds__(kWG, (min_blocks<N, P_, MODE>())) void k_walsh(cons
       const long long slot = k - kp.kbase;  // kBlock only
 
       int mx = 0;
+      // Store modes: every emit happens under `valid` (one branch per mask,
+      // not per store), through a global-address-space row pointer.
+      gint32* gdst = nullptr;
+      if constexpr (MODE == kStoreB) gdst = (gint32*)(jd.spec + ((size_t)b << N));
+      if constexpr (MODE == kStoreA) gdst = (gint32*)(jd.spec + b);
+      if constexpr (MODE == kBlock)
+        gdst = (gint32*)(kp.blockout + ((size_t)slot << (16 + kp.nblk_log)) + ((size_t)xblk << 16));
       auto emit = [&](uint32_t a, int v) {  // v = -W(a,b)/2 (or the block value)
         mx = max(mx, v < 0 ? -v : v);
-        if (valid) {
-          if constexpr (MODE == kStoreB) jd.spec[((size_t)b << N) | a] = -2 * v;
-          if constexpr (MODE == kStoreA) jd.spec[((size_t)a << jd.m) | b] = -2 * v;
-          if constexpr (MODE == kBlock)
-            kp.blockout[((size_t)slot << (16 + kp.nblk_log)) + ((size_t)xblk << 16) + a] = v;
-        }
+        // a < 2^16 here, so a 32-bit byte offset from a scalar row base suffices
+        if constexpr (MODE == kStoreB)
+          *(gint32*)((__attribute__((address_space(1))) char*)gdst + (uint32_t)(a << 2)) = -2 * v;
+        if constexpr (MODE == kStoreA) gdst[(size_t)a << jd.m] = -2 * v;
+        if constexpr (MODE == kBlock)
+          *(gint32*)((__attribute__((address_space(1))) char*)gdst + (uint32_t)(a << 2)) = v;
       };
 
       if constexpr (N < 5) {
         // ---- fewer than 32 inputs: the whole transform is popcounts
         constexpr uint32_t low = (N == 0) ? 1u : ((1u << (1 << N)) - 1u);
+        if (!STORE || valid) {
 #pragma unroll
-        for (int a = 0; a < (1 << N); ++a) {
-          const int c = __builtin_popcount((G[0] ^ walsh_mask(a)) & low) - (1 << (N - 1));
-          emit((uint32_t)a, c);
+          for (int a = 0; a < (1 << N); ++a) {
+            const int c = __builtin_popcount((G[0] ^ walsh_mask(a)) & low) - (1 << (N - 1));
+            emit((uint32_t)a, c);
+          }
         }
       } else {
         // ---- phase 1: popcount stages (x0..x4) + register stages (x5..x_{P-1})
@@ -304,11 +316,13 @@ __global__ __launch_bounds__(kWG, (min_blocks<N, P_, MODE>())) void k_walsh(cons
         if constexpr (Q == 0) {
           if constexpr (P == 5) {
             if constexpr (STORE) {
+              if (valid) {
 #pragma unroll
               for (int r = 0; r < NR; ++r) {
                 emit(aidx(r, 0), unpack_lo(R[r]));
                 emit(aidx(r, 1), unpack_hi(R[r]));
               }
+            }
             } else {
               Tracker t; t.reset();
 #pragma unroll
@@ -320,6 +334,7 @@ __global__ __launch_bounds__(kWG, (min_blocks<N, P_, MODE>())) void k_walsh(cons
             for (int d = 4; d < LAST1; ++d) stage_regs<NR>(R, 1 << d);
             constexpr int fb = 1 << LAST1;
             if constexpr (STORE) {
+              if (valid) {
 #pragma unroll
               for (int r = 0; r < NR; ++r) {
                 if (r & fb) continue;
@@ -329,6 +344,7 @@ __global__ __launch_bounds__(kWG, (min_blocks<N, P_, MODE>())) void k_walsh(cons
                 emit(aidx(r | fb, 0), unpack_lo(u) - unpack_lo(v));
                 emit(aidx(r | fb, 1), unpack_hi(u) - unpack_hi(v));
               }
+            }
             } else {
               Tracker t; t.reset();
 #pragma unroll
@@ -362,6 +378,7 @@ __global__ __launch_bounds__(kWG, (min_blocks<N, P_, MODE>())) void k_walsh(cons
             for (int d = 0; d < Q - 1; ++d) stage_regs<NR>(R, 1 << d);
             constexpr int fb = 1 << (Q - 1);
             if constexpr (STORE) {
+              if (valid) {
 #pragma unroll
               for (int r = 0; r < NR; ++r) {
                 if (r & fb) continue;
@@ -373,6 +390,7 @@ __global__ __launch_bounds__(kWG, (min_blocks<N, P_, MODE>())) void k_walsh(cons
                 emit(aidx(u, 0) | ((uint32_t)(y | fb) << P), unpack_lo(uu) - unpack_lo(vv));
                 emit(aidx(u, 1) | ((uint32_t)(y | fb) << P), unpack_hi(uu) - unpack_hi(vv));
               }
+            }
             } else {
               Tracker t; t.reset();
 #pragma unroll
@@ -433,6 +451,7 @@ __global__ __launch_bounds__(kWG, (min_blocks<N, P_, MODE>())) void k_walsh(cons
 #pragma unroll
             for (int i = 0; i < H2; ++i) swap_halves(R[i], R[i + H2]);
             if constexpr (STORE) {
+              if (valid) {
               // With the two-round exchange a wave whose physical register
               // halves are swapped (flip = tid[6] ^ u[6]) ends with the
               // lanes of h = 1 holding the negated outputs.
@@ -449,6 +468,7 @@ __global__ __launch_bounds__(kWG, (min_blocks<N, P_, MODE>())) void k_walsh(cons
                 emit(a0 + top, sgn * (unpack_lo(uu) - unpack_lo(vv)));
                 emit(a0 + top + 16, sgn * (unpack_hi(uu) - unpack_hi(vv)));
               }
+            }
             } else {
               Tracker t; t.reset();
 #pragma unroll
