@@ -183,7 +183,7 @@ constexpr int kLdsStride = kWG + 1;  // padded LDS row (odd number of words)
 // kernel with the two-round exchange fits two (<= 256 VGPRs per lane).
 template <int N, int P_, int MODE>
 constexpr int min_blocks() {
-  return (N == 16 && P_ == 8 && MODE == kMax) ? 2 : 1;
+  return (N == 16 && P_ == 8 && (MODE == kMax || MODE == kStoreB)) ? 2 : 1;
 }
 
 template <int N, int P_, int MODE>
@@ -199,7 +199,7 @@ __global__ __launch_bounds__(kWG, (min_blocks<N, P_, MODE>())) void k_walsh(cons
   constexpr int SWZ_SHIFT = (Q >= 1 && Q <= P - 1) ? (P - 1 - Q) : 0;
   constexpr int U2 = (Q >= 1 && Q <= P - 1) ? (1 << (P - 1 - Q)) : 1;
 
-  constexpr bool TWO_ROUND = (MODE == kMax && Q == P && P == 8);
+  constexpr bool TWO_ROUND = ((MODE == kMax || MODE == kStoreB) && Q == P && P == 8);
   constexpr int LDS_WORDS = (Q == 0) ? 1 : (Q <= P - 1) ? NR * kWG : (TWO_ROUND ? 64 : NR) * kLdsStride;
   __shared__ uint32_t lds[LDS_WORDS];
   __shared__ int red[kWG / 64];
