@@ -237,6 +237,7 @@ def bench_extra(torch, B, inputs, dev):
     out["12x12_slice_spectrum_a"] = single(ns["slice12"], 12, 12, 2, reps=10)
     out["12x12_slice_spectrum_b"] = single(ns["slice12"], 12, 12, 1, reps=10)
     out["16x16_perm_spectrum_b"] = single(inputs.workload_16x16()["perm"], 16, 16, 1, reps=2)
+    out["16x16_perm_spectrum_a"] = single(inputs.workload_16x16()["perm"], 16, 16, 2, reps=2)
     # component criteria (balancedness, correlation immunity, autocorrelation): two
     # transforms per mask in LDS
     for n in (8, 12, 14):

@@ -193,7 +193,19 @@ size_t large_bytes(int n, int m, long long batch) {
   return kQueueBytes + f_bytes(n, m) + align256(4 * (size_t)batch) + ((size_t)batch << n) * 4;
 }
 
+long long inverse_gray(long long j) {
+  long long r = 0;
+  for (; j; j >>= 1) r ^= j;
+  return r;
+}
+
 int mode_of(int layout) { return layout == 1 ? kStoreB : (layout == 2 ? kStoreA : kMax); }
+
+// a-major output of a large spectrum (n <= 16, n + m >= 24): rows of a block
+// of masks go through a b-major slab that a tiled transpose turns into columns.
+bool use_slab(int n, int m, int layout) { return layout == 2 && n <= 16 && n >= 6 && n + m >= 24; }
+long long slab_rows(int n, int m) { return std::min(1LL << m, std::max(64LL, (1LL << 26) >> n)); }
+size_t slab_bytes(int n, int m) { return align256((size_t)slab_rows(n, m) << n) * 4; }
 
 // Chunk and grid for a kernel with `groups` thread groups per workgroup over
 // `masks` masks per job x `njobs` jobs.
@@ -305,6 +317,61 @@ sbox_status run_single(const void* S, int n, int m, int eb, int32_t* maxabs, int
     void* args[] = {(void*)&nulljobs, &jd, &one, &queue, &nq, &lay};
     s = launch((const void*)&k_init_jobs, dim3(1), dim3(256), args, st);
     if (s) return s;
+  }
+
+  if (n <= 16 && use_slab(n, m, layout)) {
+    // b-major rows of each aligned block of masks into the slab, then transpose
+    const int p = default_split(n);
+    KFn fn = lookup_kernel(n, p, kStoreB);
+    if (!fn) return fail(SBOX_ERR_INVALID_ARG, "no kernel for n=%d", n);
+    int occ = 1;
+    s = occupancy((const void*)fn, &occ);
+    if (s) return s;
+    const int Q = n <= 8 ? 0 : n - p;
+    const int groups = kWG >> Q;
+    const long long rows = slab_rows(n, m);
+    int32_t* slab = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(ws) + kQueueBytes + f_bytes(n, m));
+    const int grid_cap = (tun && tun->grid) ? tun->grid : occ * cus;
+    int chunk = 1;
+    pick_chunk(rows, groups, grid_cap, tun ? tun->chunk : 0, &chunk);
+    const long long per_item = (long long)groups * chunk;
+    const long long M = 1LL << m;
+    int qi = 1;
+    for (long long b0 = 0; b0 < M; b0 += rows, ++qi) {
+      if (qi >= 64) {
+        int* q = queue + 1;
+        long long cnt = 63;
+        void* za[] = {&q, &cnt};
+        s = launch((const void*)&k_zero, dim3(1), dim3(256), za, st);
+        if (s) return s;
+        qi = 1;
+      }
+      // Gray indices [g^-1(j) R, g^-1(j) R + R) visit exactly the masks
+      // [j R, j R + R): the Gray code maps index block i onto mask block gray(i).
+      KParams kp{};
+      kp.job0 = jd;
+      kp.job0.spec = slab;
+      kp.njobs = 1;
+      kp.chunk = chunk;
+      kp.queue = queue + qi;
+      kp.kbase = inverse_gray(b0 / rows) * rows;
+      kp.kcount = rows;
+      kp.row0 = b0;
+      kp.rows = rows;
+      kp.total_items = (rows + per_item - 1) / per_item;
+      const int grid = (int)std::min<long long>(grid_cap, kp.total_items);
+      void* args[] = {&kp};
+      s = launch((const void*)fn, dim3(grid), dim3(kWG), args, st);
+      if (s) return s;
+      int n_ = n, m_ = m, B_ = (int)rows;
+      long long b0_ = b0;
+      int32_t* slab_ = slab;
+      void* targs[] = {&slab_, &n_, &spec, &m_, &b0_, &B_};
+      s = launch((const void*)&k_transpose_slab, dim3((unsigned)(((1LL << n) + 63) / 64), (unsigned)((rows + 63) / 64)),
+                 dim3(256), targs, st);
+      if (s) return s;
+    }
+    return SBOX_OK;
   }
 
   if (n <= 16) {
@@ -600,7 +667,7 @@ size_t sbox_walsh_nl_workspace_bytes(int n, int m, int layout) {
   if (n < 1 || n > 24 || m < 1 || m > 24 || n + m > 40) return 0;
   if (layout < 0 || layout > 2) return 0;
   if (layout != 0 && n + m > 34) return 0;
-  if (n <= 16) return kQueueBytes + f_bytes(n, m);
+  if (n <= 16) return kQueueBytes + f_bytes(n, m) + (use_slab(n, m, layout) ? slab_bytes(n, m) : 0);
   if (use_big(n, layout)) return big_bytes(n, m);
   return large_bytes(n, m, default_large_batch(n, m));
 }

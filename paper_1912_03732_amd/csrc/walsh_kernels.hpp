@@ -74,8 +74,10 @@ struct KParams {
   // n > 16, first pass: 2^16-point transforms of the 2^(n-16) blocks of x
   int32_t* blockout;     // [kcount][2^n] int32
   long long kbase;       // first Gray index of this batch of masks
-  long long kcount;      // masks in this batch
+  long long kcount;      // masks in this batch (0: all 2^m masks, block mode: required)
   int nblk_log;          // n - 16
+  long long row0;        // b-major store mode: row b goes to spec + (b - row0) * 2^n
+  long long rows;        // ... and only rows [0, rows) exist there (0: all 2^m)
 };
 
 typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));
@@ -240,8 +242,8 @@ __global__ __launch_bounds__(kWG, (min_blocks<N, P_, MODE>())) void k_walsh(cons
       jd = kp.jobs[lo];
       li = item - jd.item_begin;
     }
-    const long long kfirst = (MODE == kBlock ? kp.kbase : 0) + (li * GPW + g) * (long long)C;
-    const long long kend = (MODE == kBlock) ? (kp.kbase + kp.kcount) : (1LL << jd.m);
+    const long long kfirst = kp.kbase + (li * GPW + g) * (long long)C;
+    const long long kend = (kp.kcount > 0) ? (kp.kbase + kp.kcount) : (1LL << jd.m);
     const long long wb = (MODE == kBlock ? ((long long)xblk << 11) : 0) + (long long)tg * NW;
     const int n = jd.n;
     int runmin = 0x7fffffff;
@@ -268,15 +270,17 @@ __global__ __launch_bounds__(kWG, (min_blocks<N, P_, MODE>())) void k_walsh(cons
         const int i = __builtin_ctzll((unsigned long long)(k + 1));
         load_words<NW>(Fn, jd.F + (long long)i * jd.nwords + wb, false);
       }
-      const bool valid = inrange && k != 0;
       const uint32_t b = (uint32_t)gray(k);
+      // a b-major slab holds rows [row0, row0 + rows) only
+      const bool inslab = MODE != kStoreB || kp.rows == 0 || (unsigned long long)((long long)b - kp.row0) < (unsigned long long)kp.rows;
+      const bool valid = inrange && k != 0 && inslab;
       const long long slot = k - kp.kbase;  // kBlock only
 
       int mx = 0;
       // Store modes: every emit happens under `valid` (one branch per mask,
       // not per store), through a global-address-space row pointer.
       gint32* gdst = nullptr;
-      if constexpr (MODE == kStoreB) gdst = (gint32*)(jd.spec + ((size_t)b << N));
+      if constexpr (MODE == kStoreB) gdst = (gint32*)(jd.spec + ((size_t)(b - kp.row0) << N));
       if constexpr (MODE == kStoreA) gdst = (gint32*)(jd.spec + b);
       if constexpr (MODE == kBlock)
         gdst = (gint32*)(kp.blockout + ((size_t)slot << (16 + kp.nblk_log)) + ((size_t)xblk << 16));
@@ -891,6 +895,33 @@ __global__ void k_criteria_finish(int32_t* crit) {
     crit[5] = crit[5] - 1;
   }
 }
+// ---------------------------------------------------------------------------
+// a-major spectrum of a large box: the fused kernel writes the rows of an
+// aligned block of masks b in [b0, b0 + B) (b-major, int32) into a slab, and
+// this kernel transposes the slab into columns b0 .. b0 + B - 1 of the
+// a-major matrix through a 64 x 64 LDS tile, so that both the slab reads (along
+// a) and the spectrum writes (along b) are 256-byte runs.  Column b = 0 is
+// written by the init kernel and skipped here.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_transpose_slab(const int32_t* slab, int n, int32_t* spec, int m,
+                                                        long long b0, int B) {
+  __shared__ int32_t tile[64][65];
+  const long long N = 1LL << n;
+  const long long a0 = (long long)blockIdx.x * 64;
+  const int j0 = blockIdx.y * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int r = ty; r < 64; r += 4) {
+    const int j = j0 + r;
+    if (j < B && a0 + tx < N) tile[r][tx] = slab[(long long)j * N + a0 + tx];
+  }
+  __syncthreads();
+  for (int r = ty; r < 64; r += 4) {
+    const long long a = a0 + r;
+    const int j = j0 + tx;
+    if (j < B && a < N && b0 + j != 0) spec[(a << m) + b0 + j] = tile[tx][r];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Per-call initialisation: queue counters, NL start value 2^(n-1),
 // maxabs[0] = 2^n, and the b = 0 row / column of a requested spectrum.

@@ -94,3 +94,24 @@ def test_batched_rejects_large_n_and_bad_jobs(lib):
     st, h = B.sbox_plan_create(jobs, 1, None)
     assert st == B.SBOX_ERR_INVALID_ARG and not h
     B.sbox_plan_destroy(None)  # no-op
+
+
+def test_gray_code_block_mapping():
+    """The a-major slab path relies on this: Gray indices in block i visit
+    exactly the masks of block gray(i), so mask block j is covered by index
+    block gray^-1(j)."""
+    def gray(k):
+        return k ^ (k >> 1)
+
+    def inverse_gray(j):
+        r = 0
+        while j:
+            r ^= j
+            j >>= 1
+        return r
+    R = 64
+    for j in range(32):
+        assert sorted(gray(k) for k in range(j * R, (j + 1) * R)) == list(range(gray(j) * R, (gray(j) + 1) * R))
+        i = inverse_gray(j)
+        assert gray(i) == j
+        assert sorted(gray(k) for k in range(i * R, (i + 1) * R)) == list(range(j * R, (j + 1) * R))

@@ -212,3 +212,46 @@ def test_repeated_calls_are_deterministic():
     ref = B.walsh_nl(t, 13, 10)[1].cpu().numpy()
     for _ in range(5):
         assert np.array_equal(B.walsh_nl(t, 13, 10)[1].cpu().numpy(), ref)
+
+
+@pytest.mark.parametrize("n,m", [(8, 16), (14, 10), (16, 8), (6, 18)])
+def test_a_major_through_transposed_slabs(n, m):
+    """Large a-major spectra are written through b-major slabs and a tiled
+    transpose (n + m >= 24)."""
+    S = table(n, m, 13000 + n * m)
+    nl, mx, spec = gpu_nl(S, n, m, spectrum="a")
+    assert np.array_equal(spec, oracle.spectrum(S, n, m, oracle.A_MAJOR))
+    assert nl == oracle.walsh_nl(S, n, m, nthreads=NT)[0]
+
+
+def test_a_major_many_slabs_sampled_columns():
+    """n = 12, m = 16: four slabs of 2^14 masks; every slab's columns land in
+    place (sampled masks from each slab against the oracle)."""
+    n, m = 12, 16
+    S = table(n, m, 13050)
+    t = dev_table(S, m)
+    nl, mx, spec = B.walsh_nl(t, n, m, spectrum="a")
+    g = inputs.rng(13051)
+    for blk in range(4):
+        for b in [blk << 14, (blk << 14) + 1, ((blk + 1) << 14) - 1] + [int(v) for v in g.integers(blk << 14, (blk + 1) << 14, size=3)]:
+            col = spec[:, b].cpu().numpy()
+            assert np.array_equal(col, oracle.walsh_column(S, n, m, b)), b
+    assert nl == oracle.walsh_nl(S, n, m, nthreads=NT)[0]
+
+
+def test_a_major_16x16_sampled_columns():
+    import torch
+    S = inputs.workload_16x16()["perm"]
+    t = dev_table(S, 16)
+    nl, mx, spec = B.walsh_nl(t, 16, 16, spectrum="a")
+    g = inputs.rng(13100)
+    for b in [0, 1, 0xFFFF, 0x8000] + [int(v) for v in g.integers(1, 1 << 16, size=6)]:
+        col = spec[:, b].cpu().numpy()
+        assert np.array_equal(col, oracle.walsh_column(S, 16, 16, b)), b
+    for a in [0, 1, 0x1234]:
+        row = spec[a, :].cpu().numpy()
+        ref = np.array([oracle.walsh_entry(S, 16, a, b) for b in range(0, 1 << 16, 4099)])
+        assert np.array_equal(row[::4099], ref), a
+    assert nl == 31960
+    del spec
+    torch.cuda.empty_cache()
