@@ -21,7 +21,8 @@
  *   - Optionally the whole matrix, written as int32 in one of two layouts:
  *     SBOX_SPECTRUM_B_MAJOR: W[b * 2^n + a] (the transposed matrix of
  *     Section 5.1) or SBOX_SPECTRUM_A_MAJOR: W[a * 2^m + b] (Algorithm 1's
- *     matrix).  Without it the 2^(n+m) matrix is never materialised.
+ *     matrix), or the same layouts of the linear approximation table W/2
+ *     (SBOX_LAT_*).  Without it the 2^(n+m) matrix is never materialised.
  *   Every result is an exact integer; int32 holds all of them for n <= 30.
  *
  * Conventions for every entry point:
@@ -62,7 +63,10 @@ typedef enum {
 typedef enum {
     SBOX_SPECTRUM_NONE = 0,
     SBOX_SPECTRUM_B_MAJOR = 1, /* W[b * 2^n + a] */
-    SBOX_SPECTRUM_A_MAJOR = 2  /* W[a * 2^m + b] */
+    SBOX_SPECTRUM_A_MAJOR = 2, /* W[a * 2^m + b] */
+    SBOX_SPECTRUM_LAT = 0x10,  /* flag: store the linear approximation table W/2 instead of W */
+    SBOX_LAT_B_MAJOR = 0x11,   /* LAT[b * 2^n + a] = W(a, b) / 2 = #{x : a.x = b.S(x)} - 2^(n-1) */
+    SBOX_LAT_A_MAJOR = 0x12    /* LAT[a * 2^m + b] */
 } sbox_layout;
 
 /*

@@ -26,6 +26,9 @@ SBOX_ERR_HIP = 4
 SPECTRUM_NONE = 0
 SPECTRUM_B_MAJOR = 1
 SPECTRUM_A_MAJOR = 2
+SPECTRUM_LAT = 0x10
+LAT_B_MAJOR = 0x11
+LAT_A_MAJOR = 0x12
 
 _STATUS_NAMES = {0: "SBOX_OK", 1: "SBOX_ERR_INVALID_ARG", 2: "SBOX_ERR_UNSUPPORTED",
                  3: "SBOX_ERR_WORKSPACE", 4: "SBOX_ERR_HIP"}
@@ -212,13 +215,14 @@ def walsh_nl(S, n: int, m: int, *, spectrum: Optional[str] = None, maxabs: bool 
     if not isinstance(S, torch.Tensor) or not S.is_cuda:
         raise TypeError("S must be a device tensor")
     S = S.contiguous()
-    layout = {None: SPECTRUM_NONE, "b": SPECTRUM_B_MAJOR, "a": SPECTRUM_A_MAJOR}[spectrum]
+    layout = {None: SPECTRUM_NONE, "b": SPECTRUM_B_MAJOR, "a": SPECTRUM_A_MAJOR,
+              "lat-b": LAT_B_MAJOR, "lat-a": LAT_A_MAJOR}[spectrum]
     dev = S.device
     nl_t = torch.empty(1, dtype=torch.int32, device=dev)
     mx = torch.empty(1 << m, dtype=torch.int32, device=dev) if maxabs else None
     spec = None
     if layout != SPECTRUM_NONE:
-        shape = (1 << m, 1 << n) if layout == SPECTRUM_B_MAJOR else (1 << n, 1 << m)
+        shape = (1 << m, 1 << n) if (layout & 3) == SPECTRUM_B_MAJOR else (1 << n, 1 << m)
         spec = torch.empty(shape, dtype=torch.int32, device=dev)
     if tuning is None and layout == SPECTRUM_NONE:
         from . import autotune

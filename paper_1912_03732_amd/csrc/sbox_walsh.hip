@@ -148,9 +148,15 @@ sbox_status check_nm(int n, int m) {
   return SBOX_OK;
 }
 
+bool layout_valid(int layout) {
+  return layout == SBOX_SPECTRUM_NONE || layout == SBOX_SPECTRUM_B_MAJOR || layout == SBOX_SPECTRUM_A_MAJOR ||
+         layout == SBOX_LAT_B_MAJOR || layout == SBOX_LAT_A_MAJOR;
+}
+int base_layout(int layout) { return layout & 3; }
+int wscale_of(int layout) { return (layout & SBOX_SPECTRUM_LAT) ? -1 : -2; }
+
 sbox_status check_layout(int layout, int n, int m, const int32_t* spec) {
-  if (layout != SBOX_SPECTRUM_NONE && layout != SBOX_SPECTRUM_B_MAJOR && layout != SBOX_SPECTRUM_A_MAJOR)
-    return fail(SBOX_ERR_INVALID_ARG, "invalid spectrum layout %d", layout);
+  if (!layout_valid(layout)) return fail(SBOX_ERR_INVALID_ARG, "invalid spectrum layout %d", layout);
   if (layout != SBOX_SPECTRUM_NONE) {
     if (!spec) return fail(SBOX_ERR_INVALID_ARG, "spectrum layout %d requested with a null spectrum", layout);
     if (n + m > 34) return fail(SBOX_ERR_UNSUPPORTED, "spectrum of 2^%d coefficients is too large", n + m);
@@ -266,7 +272,9 @@ sbox_status run_big(const void* S, int n, int m, int eb, int32_t* maxabs, int32_
 
 // ------------------------------------------------------- one S-box call ----
 sbox_status run_single(const void* S, int n, int m, int eb, int32_t* maxabs, int32_t* nl, int32_t* spec,
-                       int layout, void* ws, size_t ws_bytes, const sbox_tuning* tun, hipStream_t st) {
+                       int layout_arg, void* ws, size_t ws_bytes, const sbox_tuning* tun, hipStream_t st) {
+  const int layout = base_layout(layout_arg);
+  const int wscale = wscale_of(layout_arg);
   int cus = 0;
   sbox_status s = device_info(&cus);
   if (s) return s;
@@ -281,6 +289,7 @@ sbox_status run_single(const void* S, int n, int m, int eb, int32_t* maxabs, int
     jd.nl = nl;
     jd.n = n;
     jd.m = m;
+    jd.wscale = -2;
     const JobDesc* nulljobs = nullptr;
     int one = 1, nq = 64, lay = 0;
     void* args[] = {(void*)&nulljobs, &jd, &one, &queue, &nq, &lay};
@@ -310,6 +319,7 @@ sbox_status run_single(const void* S, int n, int m, int eb, int32_t* maxabs, int
   jd.m = m;
   jd.nwords = nwords;
   jd.s_elem_bytes = eb;
+  jd.wscale = wscale;
   // init: queue counters, NL, maxabs[0], b = 0 spectrum row
   {
     const JobDesc* nulljobs = nullptr;
@@ -454,9 +464,9 @@ sbox_status run_single(const void* S, int n, int m, int eb, int32_t* maxabs, int
       const long long threads = kcount * ((1LL << 16) << (L - r));
       const unsigned blocks = (unsigned)((threads + 255) / 256);
       int32_t* spec_ = spec;
-      int lay = layout, m_ = m, L_ = L, b0 = bit0;
+      int lay = layout, ws_ = wscale, m_ = m, L_ = L, b0 = bit0;
       long long kc = kcount, kb = kbase, mend = M;
-      void* args[] = {&T, &kc, &L_, &b0, &slotmax, &spec_, &lay, &m_, &kb, &mend};
+      void* args[] = {&T, &kc, &L_, &b0, &slotmax, &spec_, &lay, &ws_, &m_, &kb, &mend};
       const void* fn = nullptr;
       if (last) {
         fn = r == 1 ? (const void*)&k_combine<1, true> : r == 2 ? (const void*)&k_combine<2, true>
@@ -543,7 +553,7 @@ sbox_status plan_batch(const sbox_job* jobs, int count, const sbox_tuning* tun, 
     c.layout = layout;
     const int p = (tun && tun->split_p && n > 8) ? tun->split_p : default_split(n);
     if (n > 8 && !split_valid(n, p)) return fail(SBOX_ERR_INVALID_ARG, "split_p=%d invalid for n=%d", p, n);
-    c.fn = lookup_kernel(n, p, mode_of(layout));
+    c.fn = lookup_kernel(n, p, mode_of(base_layout(layout)));
     if (!c.fn) return fail(SBOX_ERR_INVALID_ARG, "no kernel for n=%d split_p=%d layout=%d", n, p, layout);
     int occ = 1;
     s = occupancy((const void*)c.fn, &occ);
@@ -569,6 +579,7 @@ sbox_status plan_batch(const sbox_job* jobs, int count, const sbox_tuning* tun, 
       d.m = j.m;
       d.nwords = j.n >= 5 ? 1 << (j.n - 5) : 1;
       d.s_elem_bytes = j.s_elem_bytes;
+      d.wscale = wscale_of(j.layout);
       const long long per_item = (long long)groups * c.chunk;
       items += ((1LL << j.m) + per_item - 1) / per_item;
       L.descs.push_back(d);
@@ -612,7 +623,7 @@ sbox_status launch_batch(const BatchLayout& L, void* ws, hipStream_t st) {
   for (const ClassLaunch& c : L.classes) {
     const JobDesc* d = reinterpret_cast<const JobDesc*>(reinterpret_cast<const char*>(dtab) + c.desc_off);
     JobDesc unused{};
-    int njc = c.njobs, nq0 = 0, lay = c.layout;
+    int njc = c.njobs, nq0 = 0, lay = base_layout(c.layout);
     void* args[] = {(void*)&d, &unused, &njc, &queue, &nq0, &lay};
     s = launch((const void*)&k_init_jobs, dim3(njc), dim3(256), args, st);
     if (s) return s;
@@ -665,7 +676,8 @@ const char* sbox_version(void) { return "1.0.0"; }
 
 size_t sbox_walsh_nl_workspace_bytes(int n, int m, int layout) {
   if (n < 1 || n > 24 || m < 1 || m > 24 || n + m > 40) return 0;
-  if (layout < 0 || layout > 2) return 0;
+  if (!layout_valid(layout)) return 0;
+  layout = base_layout(layout);
   if (layout != 0 && n + m > 34) return 0;
   if (n <= 16) return kQueueBytes + f_bytes(n, m) + (use_slab(n, m, layout) ? slab_bytes(n, m) : 0);
   if (use_big(n, layout)) return big_bytes(n, m);

@@ -62,6 +62,8 @@ struct JobDesc {
   int n, m;
   int nwords;            // words per slice (2^(n-5), at least 1)
   int s_elem_bytes;
+  int wscale;            // stored value = wscale * (-W/2): -2 for W, -1 for the LAT (W/2)
+  int pad_;
 };
 
 struct KParams {
@@ -288,8 +290,8 @@ __global__ __launch_bounds__(kWG, (min_blocks<N, P_, MODE>())) void k_walsh(cons
         mx = max(mx, v < 0 ? -v : v);
         // a < 2^16 here, so a 32-bit byte offset from a scalar row base suffices
         if constexpr (MODE == kStoreB)
-          *(gint32*)((__attribute__((address_space(1))) char*)gdst + (uint32_t)(a << 2)) = -2 * v;
-        if constexpr (MODE == kStoreA) gdst[(size_t)a << jd.m] = -2 * v;
+          *(gint32*)((__attribute__((address_space(1))) char*)gdst + (uint32_t)(a << 2)) = jd.wscale * v;
+        if constexpr (MODE == kStoreA) gdst[(size_t)a << jd.m] = jd.wscale * v;
         if constexpr (MODE == kBlock)
           *(gint32*)((__attribute__((address_space(1))) char*)gdst + (uint32_t)(a << 2)) = v;
       };
@@ -941,7 +943,7 @@ __global__ __launch_bounds__(256) void k_init_jobs(const JobDesc* jobs, JobDesc 
   if (jd.spec) {
     const long long N = 1LL << jd.n;
     for (long long a = threadIdx.x; a < N; a += blockDim.x) {
-      const int v = (a == 0) ? (int)N : 0;
+      const int v = (a == 0) ? (int)(N >> 1) * -jd.wscale : 0;  // 2^n (W) or 2^(n-1) (LAT)
       if (layout == 1) jd.spec[a] = v;
       else jd.spec[a << jd.m] = v;
     }
@@ -962,7 +964,7 @@ __global__ __launch_bounds__(256) void k_zero(int* p, long long count) {
 // ---------------------------------------------------------------------------
 template <int R, bool LAST>
 __global__ __launch_bounds__(256) void k_combine(int32_t* T, long long kcount, int nblk_log, int bit0,
-                                                 int* slotmax, int32_t* spec, int layout, int m,
+                                                 int* slotmax, int32_t* spec, int layout, int wscale, int m,
                                                  long long kbase, long long mend) {
   const int L = nblk_log;
   const long long per_slot = (1LL << 16) << (L - R);  // threads per slot
@@ -997,8 +999,8 @@ __global__ __launch_bounds__(256) void k_combine(int32_t* T, long long kcount, i
         mx = max(mx, v[j] < 0 ? -v[j] : v[j]);
         if (spec && valid) {
           const long long a = alo | ((base_blk | ((long long)j << bit0)) << 16);
-          if (layout == 1) spec[((long long)b << (16 + L)) | a] = -2 * v[j];
-          else spec[(a << m) | b] = -2 * v[j];
+          if (layout == 1) spec[((long long)b << (16 + L)) | a] = wscale * v[j];
+          else spec[(a << m) | b] = wscale * v[j];
         }
       }
     } else {

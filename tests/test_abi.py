@@ -42,7 +42,8 @@ def test_version(lib):
 @pytest.mark.parametrize("n,m,layout,ok", [
     (1, 1, 0, True), (16, 16, 0, True), (24, 16, 0, True), (16, 24, 0, True),
     (0, 4, 0, False), (4, 0, 0, False), (25, 1, 0, False), (20, 21, 0, False),
-    (16, 16, 1, True), (16, 18, 2, True), (20, 16, 1, False), (4, 4, 3, False), (4, 4, -1, False)])
+    (16, 16, 1, True), (16, 18, 2, True), (20, 16, 1, False), (4, 4, 3, False), (4, 4, -1, False),
+    (8, 8, 0x11, True), (8, 8, 0x12, True), (8, 8, 0x10, False), (8, 8, 0x13, False)])
 def test_workspace_query(lib, n, m, layout, ok):
     v = B.sbox_walsh_nl_workspace_bytes(n, m, layout)
     assert (v > 0) == ok

@@ -99,7 +99,7 @@ def test_batched_with_spectra_and_edge_boxes():
         tabs.append(dev_table(S, m))
         outs_nl.append(torch.empty(1, dtype=torch.int32, device="cuda"))
         outs_mx.append(torch.empty(1 << m, dtype=torch.int32, device="cuda"))
-        lay = 1 + (i % 2)
+        lay = [1, 2, 0x11, 0x12][i % 4]
         layouts.append(lay)
         specs.append(torch.empty(1 << (n + m), dtype=torch.int32, device="cuda"))
     jobs = B.make_jobs(tabs, [b[0] for b in boxes], [b[1] for b in boxes], outs_nl, outs_mx, layouts, specs)
@@ -109,8 +109,10 @@ def test_batched_with_spectra_and_edge_boxes():
     assert st == 0, B.last_error()
     torch.cuda.synchronize()
     for i, (n, m) in enumerate(boxes):
-        lay = oracle.B_MAJOR if layouts[i] == 1 else oracle.A_MAJOR
+        lay = oracle.B_MAJOR if (layouts[i] & 3) == 1 else oracle.A_MAJOR
         ref = oracle.spectrum(Ss[i], n, m, lay).reshape(-1)
+        if layouts[i] & 0x10:
+            ref = ref // 2
         assert np.array_equal(specs[i].cpu().numpy(), ref), (n, m, layouts[i])
         assert int(outs_nl[i].item()) == oracle.walsh_nl(Ss[i], n, m)[0]
 

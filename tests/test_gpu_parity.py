@@ -255,3 +255,20 @@ def test_a_major_16x16_sampled_columns():
     assert nl == 31960
     del spec
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("n,m,kind", [(3, 4, "lat-b"), (8, 8, "lat-a"), (11, 5, "lat-b"), (16, 3, "lat-a"),
+                                      (12, 12, "lat-a"), (17, 2, "lat-b")])
+def test_linear_approximation_table(n, m, kind):
+    """LAT(a, b) = W(a, b) / 2 = #{x : a.x = b.S(x)} - 2^(n-1)."""
+    S = table(n, m, 14000 + n * m)
+    nl, mx, lat = gpu_nl(S, n, m, spectrum=kind)
+    ref = oracle.spectrum(S, n, m, oracle.B_MAJOR if kind == "lat-b" else oracle.A_MAJOR) // 2
+    assert np.array_equal(lat, ref)
+    if n <= 8:
+        # the counting definition, for a few entries
+        x = np.arange(1 << n)
+        for a, b in [(0, 1), (3, (1 << m) - 1), ((1 << n) - 1, 1)]:
+            eq = (np.bitwise_count((a & x).astype(np.uint64)) & 1) == (np.bitwise_count((b & S.astype(np.int64)).astype(np.uint64)) & 1)
+            v = int(eq.sum()) - (1 << (n - 1))
+            assert (lat[b, a] if kind == "lat-b" else lat[a, b]) == v
