@@ -33,7 +33,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--cpu-sample-masks", type=int, default=8192,
+    ap.add_argument("--cpu-sample-masks", type=int, default=32768,
                     help="masks of the 16x16 box the CPU oracle is timed on")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--batched", action="store_true", help="also time the mixed 4096-box batch")
@@ -41,18 +41,30 @@ def parse():
     ap.add_argument("--serving-count", type=int, default=5000, help="requests per rate in the sweep")
     ap.add_argument("--extra", action="store_true",
                     help="also time the other workloads (8x8, 20x16, 16x20, 12x12 slice, 16x16 spectrum)")
+    ap.add_argument("--variant", type=int, default=0, choices=(0, 1, 2),
+                    help="butterfly engine for the 16x16 kernel: 0 library default, 1 VALU, 2 matrix cores")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters) and exit")
     return ap.parse_args()
 
 
-def measured_traffic():
+# The fused 16x16 kernel each butterfly engine launches, and the file holding
+# its rocprofv3 FETCH_SIZE / WRITE_SIZE figures.
+# Arithmetic type: packed int16 butterflies, or fp16 operands with fp32
+# accumulation on the matrix cores (every value is an integer of at most
+# 2^11 in magnitude when it is an fp16 operand, so both are exact).
+KERNELS = {1: ("k_walsh<16,8,0>", "k_walsh_16x16_traffic.json", "i16"),
+           2: ("k_walsh_mfma16", "k_walsh_mfma16_16x16_traffic.json", "f16")}
+DEFAULT_VARIANT = 2
+
+
+def measured_traffic(fname):
     """HBM bytes per dispatch of the fused 16x16 kernel from the committed
     rocprofv3 FETCH_SIZE / WRITE_SIZE runs, or None if the kernel source has
     changed since they were taken."""
     import hashlib
     try:
-        with open(os.path.join(ROOT, "profiles", "k_walsh_16x16_traffic.json")) as f:
+        with open(os.path.join(ROOT, "profiles", fname)) as f:
             rec = json.load(f)
         with open(os.path.join(ROOT, "paper_1912_03732_amd", "csrc", "walsh_kernels.hpp"), "rb") as f:
             sha = hashlib.sha256(f.read()).hexdigest()[:16]
@@ -114,9 +126,12 @@ def main():
     stream = torch.cuda.current_stream(dev)
     sptr = int(stream.cuda_stream)
 
+    tuning = B.sbox_tuning(0, 0, 0, args.variant) if args.variant else None
+    kname, tfile, dtype = KERNELS[args.variant or DEFAULT_VARIANT]
+
     def step():
         st = B.sbox_walsh_nl_ex(S.data_ptr(), n, m, 2, mx.data_ptr(), nl.data_ptr(), 0, 0,
-                                ws.ptr, ws.nbytes, None, sptr)
+                                ws.ptr, ws.nbytes, tuning, sptr)
         if st != 0:
             raise RuntimeError(B.last_error())
 
@@ -153,14 +168,14 @@ def main():
         "higher_is_better": True,
         "scaling": "strong",
         "vs_baseline": None,
-        "dtype": "i16",
+        "dtype": dtype,
         "data": "synthetic",
         "config": {"workload": "single 16x16 S-box, seeded Fisher-Yates permutation (seed %d), fused "
                                "max|W| per mask + NL, no spectrum" % (inputs.SEED_BASE + 2),
                    "n": n, "m": m, "masks": (1 << m) - 1, "nl": nl_val},
         "roofline": {"bound": "alu", "achieved": achieved_tops, "peak": PEAK_PK16_TOPS, "unit": "TOP/s",
-                     "frac": achieved_tops / PEAK_PK16_TOPS, "traffic": measured_traffic(),
-                     "kernel": "k_walsh<16,8,0>", "kernel_ms": ev_mean,
+                     "frac": achieved_tops / PEAK_PK16_TOPS, "traffic": measured_traffic(tfile),
+                     "kernel": kname, "kernel_ms": ev_mean,
                      "int32_valu_peak": PEAK_INT32_TOPS,
                      "int32_valu_frac": achieved_tops / PEAK_INT32_TOPS},
     }

@@ -77,12 +77,17 @@ typedef enum {
  *   chunk   : consecutive masks (in Gray-code order) one thread group
  *             walks per work item.
  *   grid    : number of persistent workgroups (0: fill every CU).
+ *   variant : butterfly engine for the n = 16 fused maximum (no spectrum):
+ *             0 the library's choice (currently 2), 1 packed 16-bit VALU
+ *             butterflies, 2 matrix cores (fp16 MFMA Hadamard blocks, exact);
+ *             other sizes and modes accept 0 or 1 only.  Batched launches
+ *             and plans apply it to their n = 16 boxes.
  */
 typedef struct sbox_tuning {
     int32_t split_p;
     int32_t chunk;
     int32_t grid;
-    int32_t reserved;
+    int32_t variant;
 } sbox_tuning;
 
 /*

@@ -37,14 +37,17 @@ def valid_splits(n: int) -> List[int]:
 
 
 def candidates(n: int, m: int, cus: int = 256) -> List[Tuple[int, int, int]]:
-    """(split_p, chunk, grid) triples; grid 0 means 'fill every CU'."""
+    """(split_p, chunk, grid, variant) tuples; grid 0 means 'fill every CU'."""
     out = []
     chunks = [1, 2, 4, 8, 16, 32, 64]
     grids = [0] if n >= 13 else [0, cus, 2 * cus]
     for p in valid_splits(n):
         for c in chunks:
             for g in grids:
-                out.append((p if n > 8 else 0, c, g))
+                out.append((p if n > 8 else 0, c, g, 1 if n == 16 else 0))
+    if n == 16:  # the matrix-core engine
+        for c in chunks:
+            out.append((0, c, 0, 2))
     return out
 
 
@@ -101,7 +104,7 @@ def lookup(n: int, m: int):
     if not v:
         return None
     from . import binding as B
-    return B.sbox_tuning(int(v["split_p"]), int(v["chunk"]), int(v["grid"]), 0)
+    return B.sbox_tuning(int(v["split_p"]), int(v["chunk"]), int(v["grid"]), int(v.get("variant", 0)))
 
 
 def _time(fn, reps: int) -> float:
@@ -149,20 +152,21 @@ def tune(n: int, m: int, reps: int = 3, seed: int = 191203732, save: bool = True
     cands = candidates(n, m, cus)
     if max_candidates:
         cands = cands[:max_candidates]
-    for (p, c, gr) in cands:
-        t = B.sbox_tuning(p, c, gr, 0)
+    for (p, c, gr, var) in cands:
+        t = B.sbox_tuning(p, c, gr, var)
         try:
             ms = _time(lambda: run(t), reps)
         except B.SboxError as e:
-            results.append({"split_p": p, "chunk": c, "grid": gr, "ms": None, "exact": False, "error": str(e)})
+            results.append({"split_p": p, "chunk": c, "grid": gr, "variant": var, "ms": None, "exact": False,
+                            "error": str(e)})
             continue
         exact = bool(torch.equal(mx, ref_mx)) and int(nl.item()) == ref_nl
-        results.append({"split_p": p, "chunk": c, "grid": gr, "ms": ms, "exact": exact})
+        results.append({"split_p": p, "chunk": c, "grid": gr, "variant": var, "ms": ms, "exact": exact})
     ok = [r for r in results if r["exact"] and r["ms"] is not None]
     best = min(ok, key=lambda r: r["ms"]) if ok else None
     if best and save:
         arch, ver = _arch_and_version()
-        store(key(arch, ver, n, m), {k: best[k] for k in ("split_p", "chunk", "grid", "ms")})
+        store(key(arch, ver, n, m), {k: best[k] for k in ("split_p", "chunk", "grid", "variant", "ms")})
     return {"best": best, "results": results}
 
 

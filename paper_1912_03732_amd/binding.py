@@ -42,7 +42,7 @@ class SboxError(RuntimeError):
 
 class sbox_tuning(ctypes.Structure):
     _fields_ = [("split_p", ctypes.c_int32), ("chunk", ctypes.c_int32),
-                ("grid", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("grid", ctypes.c_int32), ("variant", ctypes.c_int32)]
 
 
 class sbox_job(ctypes.Structure):

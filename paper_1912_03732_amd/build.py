@@ -20,6 +20,9 @@ HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=" + ARCH,
     # keep hipcc from fusing fp32 work into packed-fp32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # the only floating point here (fp16/fp32 MFMA Hadamard passes) holds finite
+    # integers: no NaN handling and no IEEE-mode canonicalisation around max
+    "-fno-honor-nans", "-mno-amdgpu-ieee",
     "-Wall", "-Wno-unused-function",
 ]
 

@@ -205,6 +205,14 @@ long long inverse_gray(long long j) {
   return r;
 }
 
+// Butterfly engine of the n = 16 fused maximum: the library default is the
+// matrix-core kernel (variant 2); variant 1 selects the packed 16-bit VALU one.
+constexpr int kDefaultVariant16 = 2;
+bool use_mfma16(const sbox_tuning* tun) {
+  const int v = (tun && tun->variant) ? tun->variant : kDefaultVariant16;
+  return v == 2;
+}
+
 int mode_of(int layout) { return layout == 1 ? kStoreB : (layout == 2 ? kStoreA : kMax); }
 
 // a-major output of a large spectrum (n <= 16, n + m >= 24): rows of a block
@@ -384,6 +392,26 @@ sbox_status run_single(const void* S, int n, int m, int eb, int32_t* maxabs, int
     return SBOX_OK;
   }
 
+  if (n == 16 && layout == 0 && use_mfma16(tun)) {
+    const void* fn = (const void*)&k_walsh_mfma16;
+    int occ = 1;
+    s = occupancy(fn, &occ);
+    if (s) return s;
+    const long long M = 1LL << m;
+    const int grid_cap = (tun && tun->grid) ? tun->grid : occ * cus;
+    int chunk = 1;
+    pick_chunk(M, 1, grid_cap, tun ? tun->chunk : 0, &chunk);
+    KParams kp{};
+    kp.job0 = jd;
+    kp.njobs = 1;
+    kp.chunk = chunk;
+    kp.queue = queue;
+    kp.total_items = (M + chunk - 1) / chunk;
+    const int grid = (int)std::min<long long>(grid_cap, kp.total_items);
+    void* args[] = {&kp};
+    return launch(fn, dim3(grid), dim3(kWG), args, st);
+  }
+
   if (n <= 16) {
     const int p = (tun && tun->split_p) ? tun->split_p : default_split(n);
     const int mode = mode_of(layout);
@@ -553,7 +581,8 @@ sbox_status plan_batch(const sbox_job* jobs, int count, const sbox_tuning* tun, 
     c.layout = layout;
     const int p = (tun && tun->split_p && n > 8) ? tun->split_p : default_split(n);
     if (n > 8 && !split_valid(n, p)) return fail(SBOX_ERR_INVALID_ARG, "split_p=%d invalid for n=%d", p, n);
-    c.fn = lookup_kernel(n, p, mode_of(base_layout(layout)));
+    c.fn = (n == 16 && layout == 0 && use_mfma16(tun)) ? &k_walsh_mfma16
+                                                       : lookup_kernel(n, p, mode_of(base_layout(layout)));
     if (!c.fn) return fail(SBOX_ERR_INVALID_ARG, "no kernel for n=%d split_p=%d layout=%d", n, p, layout);
     int occ = 1;
     s = occupancy((const void*)c.fn, &occ);
@@ -698,6 +727,10 @@ sbox_status sbox_walsh_nl_ex(const void* S, int n, int m, int s_elem_bytes, int3
   if (tuning) {
     if (tuning->chunk < 0 || tuning->grid < 0 || tuning->split_p < 0)
       return fail(SBOX_ERR_INVALID_ARG, "negative tuning field");
+    if (tuning->variant < 0 || tuning->variant > 2)
+      return fail(SBOX_ERR_INVALID_ARG, "tuning variant %d (0, 1 or 2)", tuning->variant);
+    if (tuning->variant == 2 && !(n == 16 && layout == 0))
+      return fail(SBOX_ERR_INVALID_ARG, "the matrix-core variant covers n = 16 without a spectrum only");
     if (tuning->split_p && n > 8 && n <= 16 && !split_valid(n, tuning->split_p))
       return fail(SBOX_ERR_INVALID_ARG, "split_p=%d invalid for n=%d", tuning->split_p, n);
     if (tuning->split_p && n <= 16 && n > 8 && layout != 0 && tuning->split_p != default_split(n))
@@ -842,6 +875,8 @@ sbox_status sbox_plan_create(const sbox_job* jobs, int32_t count, const sbox_tun
   *out = nullptr;
   if (tuning && (tuning->chunk < 0 || tuning->grid < 0 || tuning->split_p < 0))
     return fail(SBOX_ERR_INVALID_ARG, "negative tuning field");
+  if (tuning && (tuning->variant < 0 || tuning->variant > 2))
+    return fail(SBOX_ERR_INVALID_ARG, "tuning variant %d (0, 1 or 2)", tuning->variant);
   sbox_plan* p = new sbox_plan();
   sbox_status s = plan_batch(jobs, count, tuning, &p->layout);
   if (s) {

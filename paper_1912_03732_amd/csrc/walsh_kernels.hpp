@@ -519,6 +519,207 @@ __global__ __launch_bounds__(kWG, (min_blocks<N, P_, MODE>())) void k_walsh(cons
 }
 
 // ---------------------------------------------------------------------------
+// n = 16, max mode, matrix-core variant.
+//
+// Bits of x: x0..x4 inside a word (popcount stages, as above); x5..x7 index
+// a thread's 8 words; x8..x15 = t, the thread in the workgroup.
+//   1. Popcount stages, written straight as fp16: bcnt(G ^ L(a'), 0x6600 - 16)
+//      is the bit pattern of 1536 + c' (the fp16 binade [1024, 2048) has unit
+//      spacing), two of them are packed over x5 and 1536 is subtracted in
+//      fp16, exactly.  Registers R[a'][v], v = (x6, x7), each a pair over x5.
+//   2. Two packed-fp16 butterfly stages over x6, x7 (|value| <= 64, exact).
+//   3. Exchange through LDS so that wave w holds the outputs with
+//      (a6, a7) = w for every t, lane l keeps t mod 64 and register
+//      R[a'][q] receives the pair from the thread t = l + 64 q.  In two rounds
+//      of 64 KiB (a' < 16, then a' >= 16), each round refilling the registers
+//      it has just stored.
+//   4. For each a': the 8 fp16 of R[a'][0..3] are the A operand (16 x 32) of
+//      v_mfma_f32_16x16x32_f16 with rows = t mod 16 and the 32 K slots =
+//      (x5, t bits 4..7); two MFMAs against the two 16-column halves of H_32
+//      transform those 5 bits (|value| <= 2048, exact in fp32).
+//   5. Each result tile (rows = t mod 16, columns = the new 5-bit index), cast
+//      to fp16 (exact: |value| <= 2048), is the A operand of
+//      v_mfma_f32_16x16x16_f16 against H_16, which transforms t mod 16.
+//   6. |value| <= 2^15 at the end, exact in fp32; the maximum is taken with
+//      abs modifiers.
+// Every bit of x is transformed exactly once (5 + 2 + 5 + 4); which output
+// index lands where does not matter for the maximum.
+// ---------------------------------------------------------------------------
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint32_t pkf16_add(uint32_t a, uint32_t b) {
+  return __builtin_bit_cast(uint32_t, __builtin_bit_cast(f16x2, a) + __builtin_bit_cast(f16x2, b));
+}
+__device__ __forceinline__ uint32_t pkf16_sub(uint32_t a, uint32_t b) {
+  return __builtin_bit_cast(uint32_t, __builtin_bit_cast(f16x2, a) - __builtin_bit_cast(f16x2, b));
+}
+__device__ __forceinline__ _Float16 hsign(int bits) { return (__builtin_popcount(bits) & 1) ? (_Float16)-1.0f : (_Float16)1.0f; }
+
+__global__ __launch_bounds__(kWG, 2) void k_walsh_mfma16(const KParams kp) {
+  constexpr int NW = 8;
+  constexpr int LDSW = 16 * 4 * 4 * 64;  // one round: 16 a' x 4 (a6,a7) x 4 source waves x 64 lanes
+  __shared__ uint32_t lds[LDSW];
+  __shared__ int red[kWG / 64];
+  __shared__ long long s_item;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int C = kp.chunk;
+
+  // Constant B operands.  Pass 1 slot (g = lane/16, j) is the 5-bit index
+  // kappa = j + 8 g; column n = lane % 16 (+ 16 for the second half).
+  f16x8 hb0, hb1;
+  {
+    const int g = lane >> 4, n = lane & 15;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int kappa = j + 8 * g;
+      hb0[j] = hsign(kappa & n);
+      hb1[j] = hsign(kappa & (n + 16));
+    }
+  }
+  f16x4 hc;
+  {
+    const int g = lane >> 4, n = lane & 15;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) hc[j] = hsign((j + 4 * g) & n);
+  }
+
+  for (;;) {
+    if (tid == 0) s_item = (long long)atomicAdd(kp.queue, 1);
+    __syncthreads();
+    const long long item = __builtin_amdgcn_readfirstlane((int)s_item);
+    __syncthreads();
+    if (item >= kp.total_items) break;
+    JobDesc jd;
+    long long li;
+    if (kp.jobs == nullptr) {
+      jd = kp.job0;
+      li = item;
+    } else {  // batched: find the job owning this item
+      int lo = 0, hi = kp.njobs - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (kp.jobs[mid].item_begin <= item) lo = mid; else hi = mid - 1;
+      }
+      jd = kp.jobs[lo];
+      li = item - jd.item_begin;
+    }
+    const long long kfirst = li * (long long)C;
+    const long long kend = 1LL << jd.m;
+    const long long wb = (long long)tid * NW;
+    const int n = jd.n;
+    int runmin = 0x7fffffff;
+    uint32_t G[NW], Fn[NW];
+
+    for (int step = 0; step < C; ++step) {
+      const long long k = kfirst + step;
+      const bool inrange = k < kend;
+      if (step == 0) {
+#pragma unroll
+        for (int w = 0; w < NW; ++w) G[w] = 0;
+        if (inrange) {
+          const long long gk = gray(k);
+          for (int i = 0; i < jd.m; ++i)
+            if ((gk >> i) & 1) load_words<NW>(G, jd.F + (long long)i * jd.nwords + wb, true);
+        }
+      } else if (inrange) {
+#pragma unroll
+        for (int w = 0; w < NW; ++w) G[w] ^= Fn[w];
+      }
+      if (step + 1 < C && k + 1 < kend) {
+        const int i = __builtin_ctzll((unsigned long long)(k + 1));
+        load_words<NW>(Fn, jd.F + (long long)i * jd.nwords + wb, false);
+      }
+      const bool valid = inrange && k != 0;
+      const uint32_t b = (uint32_t)gray(k);
+
+      // ---- 1. popcount stages as fp16, pairs over x5
+      uint32_t R[32][4];
+      const uint32_t bias = 0x66006600u;  // fp16 1536 in both halves
+#pragma unroll
+      for (int a = 0; a < 32; ++a) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const uint32_t c0 = __builtin_popcount(G[2 * v] ^ walsh_mask(a)) + (0x6600 - 16);
+          const uint32_t c1 = __builtin_popcount(G[2 * v + 1] ^ walsh_mask(a)) + (0x6600 - 16);
+          R[a][v] = pkf16_sub(__builtin_amdgcn_perm(c1, c0, 0x05040100u), bias);
+        }
+      }
+      // ---- 2. stages over x6, x7 (v bits)
+#pragma unroll
+      for (int a = 0; a < 32; ++a) {
+        uint32_t t0 = pkf16_add(R[a][0], R[a][1]), t1 = pkf16_sub(R[a][0], R[a][1]);
+        uint32_t t2 = pkf16_add(R[a][2], R[a][3]), t3 = pkf16_sub(R[a][2], R[a][3]);
+        R[a][0] = pkf16_add(t0, t2);
+        R[a][2] = pkf16_sub(t0, t2);
+        R[a][1] = pkf16_add(t1, t3);
+        R[a][3] = pkf16_sub(t1, t3);
+      }
+      // ---- 3. exchange: R[a'][v] of thread (s = wave, l) -> R[a'][q = s] of thread (w = v, l)
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+#pragma unroll
+        for (int a = 0; a < 16; ++a)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) lds[((a * 4 + v) * 4 + wave) * 64 + lane] = R[r * 16 + a][v];
+        __syncthreads();
+#pragma unroll
+        for (int a = 0; a < 16; ++a)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) R[r * 16 + a][q] = lds[((a * 4 + wave) * 4 + q) * 64 + lane];
+        __syncthreads();
+      }
+      // ---- 4-6. matrix-core passes and the maximum
+      float mxf = 0.0f;
+#pragma unroll
+      for (int a = 0; a < 32; ++a) {
+        f16x8 av;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const f16x2 pr = __builtin_bit_cast(f16x2, R[a][q]);
+          av[2 * q] = pr[0];
+          av[2 * q + 1] = pr[1];
+        }
+        const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+        const f32x4 d0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(av, hb0, zero, 0, 0, 0);
+        const f32x4 d1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(av, hb1, zero, 0, 0, 0);
+        f16x4 a0, a1;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          a0[j] = (_Float16)d0[j];
+          a1[j] = (_Float16)d1[j];
+        }
+        const f32x4 e0 = __builtin_amdgcn_mfma_f32_16x16x16f16(a0, hc, zero, 0, 0, 0);
+        const f32x4 e1 = __builtin_amdgcn_mfma_f32_16x16x16f16(a1, hc, zero, 0, 0, 0);
+        // pairwise |.| maxima, then into the running maximum (v_max with abs
+        // modifiers, then v_max3); the compiler inserts the wait states an
+        // MFMA result needs before a VALU reads it
+        const float p0 = fmaxf(fabsf(e0[0]), fabsf(e1[0])), p1 = fmaxf(fabsf(e0[1]), fabsf(e1[1]));
+        const float p2 = fmaxf(fabsf(e0[2]), fabsf(e1[2])), p3 = fmaxf(fabsf(e0[3]), fabsf(e1[3]));
+        mxf = fmaxf(fmaxf(mxf, p0), p1);
+        mxf = fmaxf(fmaxf(mxf, p2), p3);
+      }
+      int mx = (int)mxf;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) mx = max(mx, __shfl_xor(mx, o, 64));
+      if (lane == 0) red[wave] = mx;
+      __syncthreads();
+      mx = max(max(red[0], red[1]), max(red[2], red[3]));
+      if (tid == 0 && valid) {
+        if (jd.maxabs) jd.maxabs[b] = 2 * mx;
+        runmin = min(runmin, (1 << (n - 1)) - mx);
+      }
+    }
+    if (tid == 0 && runmin != 0x7fffffff) atomicMin(jd.nl, runmin);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // n = 16 + L, 1 <= L <= 4, max mode: recompute instead of materialising.
 //
 // Write x = (x_hi : L bits, x_lo : 16 bits).  For a fixed high output index

@@ -20,11 +20,12 @@ def test_valid_splits_match_the_compiled_kernels():
 
 def test_candidates_cover_chunks_and_grids():
     c = autotune.candidates(12, 12, cus=256)
-    assert (6, 1, 0) in c and (8, 64, 512) in c
-    assert all(p in (6, 7, 8) for p, _, _ in c)
+    assert (6, 1, 0, 0) in c and (8, 64, 512, 0) in c
+    assert all(p in (6, 7, 8) for p, _, _, _ in c)
     c16 = autotune.candidates(16, 16)
-    assert {p for p, _, _ in c16} == {8} and {g for _, _, g in c16} == {0}
-    assert {p for p, _, _ in autotune.candidates(7, 7)} == {0}
+    assert {p for p, _, _, v in c16 if v == 1} == {8} and {g for _, _, g, _ in c16} == {0}
+    assert {v for _, _, _, v in c16} == {1, 2}
+    assert {p for p, _, _, _ in autotune.candidates(7, 7)} == {0}
 
 
 def test_cache_round_trip(tmp_path, monkeypatch):

@@ -119,3 +119,24 @@ def test_batched_with_spectra_and_edge_boxes():
 
 def test_empty_batch():
     assert B.sbox_walsh_nl_batched(None, 0, 0, 0, 0) == B.SBOX_OK
+
+
+@pytest.mark.parametrize("variant", [1, 2])
+def test_batched_n16_boxes_both_engines(variant):
+    """n = 16 boxes in a mixed batch (matrix-core and VALU engines) equal the oracle."""
+    import torch
+    g = inputs.rng(10051)
+    boxes = [(16, 16, inputs.permutation(16, g)), (16, 3, inputs.random_function(16, 3, g)),
+             (12, 9, inputs.random_function(12, 9, g)), (16, 7, inputs.random_function(16, 7, g)),
+             (5, 5, inputs.permutation(5, g))]
+    tabs = [dev_table(S, m) for n, m, S in boxes]
+    plan = B.Plan(tabs, [b[0] for b in boxes], [b[1] for b in boxes], tuning=B.sbox_tuning(0, 0, 0, variant))
+    for _ in range(2):
+        plan.launch()
+        torch.cuda.synchronize()
+        nl = plan.nl.cpu().numpy()
+        for i, (n, m, S) in enumerate(boxes):
+            onl, omx = oracle.walsh_nl(S, n, m, nthreads=8)
+            assert nl[i] == onl, (variant, i, n, m)
+            assert np.array_equal(plan.maxabs[i].cpu().numpy(), omx), (variant, i, n, m)
+    plan.close()

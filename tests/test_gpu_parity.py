@@ -272,3 +272,40 @@ def test_linear_approximation_table(n, m, kind):
             eq = (np.bitwise_count((a & x).astype(np.uint64)) & 1) == (np.bitwise_count((b & S.astype(np.int64)).astype(np.uint64)) & 1)
             v = int(eq.sum()) - (1 << (n - 1))
             assert (lat[b, a] if kind == "lat-b" else lat[a, b]) == v
+
+
+@pytest.mark.parametrize("m,kind", [(1, "random"), (3, "random"), (8, "random"), (11, "random"), (16, "perm"),
+                                    (16, "inv"), (16, "const")])
+def test_matrix_core_variant_16(m, kind):
+    """n = 16 fused maximum on the matrix cores (tuning variant 2), bit-exact."""
+    if kind == "perm":
+        S = inputs.workload_16x16()["perm"]
+    elif kind == "inv":
+        S = inputs.workload_16x16()["inv"]
+    elif kind == "const":
+        S = (inputs.permutation(16, inputs.rng(6001)).astype(np.uint32) & 0x7FFF).astype(np.uint16)
+    else:
+        S = table(16, m, 15000 + m)
+    nl, mx = check_against_oracle(S, 16, m, nthreads=NT, tuning=B.sbox_tuning(0, 0, 0, 2))
+    if kind == "inv":
+        assert nl == 32512
+    if kind == "const":
+        assert mx[0x8000] == 65536
+
+
+@pytest.mark.parametrize("m,kind", [(5, "random"), (16, "perm"), (16, "const")])
+def test_valu_variant_16(m, kind):
+    """The packed 16-bit VALU kernel (tuning variant 1) stays bit-exact too."""
+    if kind == "perm":
+        S = inputs.workload_16x16()["perm"]
+    elif kind == "const":
+        S = (inputs.permutation(16, inputs.rng(6001)).astype(np.uint32) & 0x7FFF).astype(np.uint16)
+    else:
+        S = table(16, m, 15200 + m)
+    check_against_oracle(S, 16, m, nthreads=NT, tuning=B.sbox_tuning(0, 0, 0, 1))
+
+
+@pytest.mark.parametrize("chunk,grid", [(1, 1), (7, 33), (64, 0)])
+def test_matrix_core_variant_launch_shapes(chunk, grid):
+    S = table(16, 9, 15100 + chunk)
+    check_against_oracle(S, 16, 9, nthreads=NT, tuning=B.sbox_tuning(0, chunk, grid, 2))
