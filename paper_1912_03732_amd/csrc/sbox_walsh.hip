@@ -208,6 +208,11 @@ long long inverse_gray(long long j) {
 // Butterfly engine of the n = 16 fused maximum: the library default is the
 // matrix-core kernel (variant 2); variant 1 selects the packed 16-bit VALU one.
 constexpr int kDefaultVariant16 = 2;
+// LDS exchange rounds of the matrix-core kernel (2: 64 KiB, 4: 32 KiB per workgroup)
+#ifndef SBW_MFMA_ROUNDS
+#define SBW_MFMA_ROUNDS 4
+#endif
+constexpr int kMfmaRounds = SBW_MFMA_ROUNDS;
 bool use_mfma16(const sbox_tuning* tun) {
   const int v = (tun && tun->variant) ? tun->variant : kDefaultVariant16;
   return v == 2;
@@ -393,7 +398,7 @@ sbox_status run_single(const void* S, int n, int m, int eb, int32_t* maxabs, int
   }
 
   if (n == 16 && layout == 0 && use_mfma16(tun)) {
-    const void* fn = (const void*)&k_walsh_mfma16;
+    const void* fn = (const void*)&k_walsh_mfma16<kMfmaRounds>;
     int occ = 1;
     s = occupancy(fn, &occ);
     if (s) return s;
@@ -581,7 +586,7 @@ sbox_status plan_batch(const sbox_job* jobs, int count, const sbox_tuning* tun, 
     c.layout = layout;
     const int p = (tun && tun->split_p && n > 8) ? tun->split_p : default_split(n);
     if (n > 8 && !split_valid(n, p)) return fail(SBOX_ERR_INVALID_ARG, "split_p=%d invalid for n=%d", p, n);
-    c.fn = (n == 16 && layout == 0 && use_mfma16(tun)) ? &k_walsh_mfma16
+    c.fn = (n == 16 && layout == 0 && use_mfma16(tun)) ? &k_walsh_mfma16<kMfmaRounds>
                                                        : lookup_kernel(n, p, mode_of(base_layout(layout)));
     if (!c.fn) return fail(SBOX_ERR_INVALID_ARG, "no kernel for n=%d split_p=%d layout=%d", n, p, layout);
     int occ = 1;

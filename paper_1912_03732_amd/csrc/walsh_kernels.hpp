@@ -522,31 +522,36 @@ __global__ __launch_bounds__(kWG, (min_blocks<N, P_, MODE>())) void k_walsh(cons
 // n = 16, max mode, matrix-core variant.
 //
 // Bits of x: x0..x4 inside a word (popcount stages, as above); x5..x7 index
-// a thread's 8 words; x8..x15 = t, the thread in the workgroup.
-//   1. Popcount stages, written straight as fp16: bcnt(G ^ L(a'), 0x6600 - 16)
-//      is the bit pattern of 1536 + c' (the fp16 binade [1024, 2048) has unit
-//      spacing), two of them are packed over x5 and 1536 is subtracted in
-//      fp16, exactly.  Registers R[a'][v], v = (x6, x7), each a pair over x5.
-//   2. Two packed-fp16 butterfly stages over x6, x7 (|value| <= 64, exact).
-//   3. Exchange through LDS so that wave w holds the outputs with
-//      (a6, a7) = w for every t, lane l keeps t mod 64 and register
-//      R[a'][q] receives the pair from the thread t = l + 64 q.  In two rounds
-//      of 64 KiB (a' < 16, then a' >= 16), each round refilling the registers
-//      it has just stored.
-//   4. For each a': the 8 fp16 of R[a'][0..3] are the A operand (16 x 32) of
-//      v_mfma_f32_16x16x32_f16 with rows = t mod 16 and the 32 K slots =
-//      (x5, t bits 4..7); two MFMAs against the two 16-column halves of H_32
-//      transform those 5 bits (|value| <= 2048, exact in fp32).
-//   5. Each result tile (rows = t mod 16, columns = the new 5-bit index), cast
-//      to fp16 (exact: |value| <= 2048), is the A operand of
-//      v_mfma_f32_16x16x16_f16 against H_16, which transforms t mod 16.
+// a thread's 8 words; x8..x15 = t, the thread in the workgroup (lane bits
+// x8..x13, wave bits x14, x15).
+//   1. Popcount stages, written straight as fp16 bit patterns:
+//      bcnt(G ^ L(a'), 0x6600 - 16) is the pattern of 1536 + c' (the fp16
+//      binade [1024, 2048) has unit spacing); two of them are packed over x5.
+//      The offset 1536 is left in: it is uniform over every input of the
+//      next transform, and a Hadamard column other than the first sums to
+//      zero, so it only adds 32 * 1536 to output column 0 of that transform,
+//      which the MFMA's accumulator input takes off again.
+//   2. Exchange through LDS so that wave w receives the a' with a' >> 3 = w
+//      from all four waves: lane l keeps t mod 64 and the register for
+//      (a', v = (x6, x7), s) holds the x5 pair of thread t = l + 64 s.  In R
+//      rounds (a' bits 1, 2 ... select the round), each small enough that
+//      several workgroups share a CU.
+//   3. Pass 1, for each (a', v): the 8 fp16 over (x5, s) are the A operand
+//      (16 x 32, rows = t mod 16, K slots = (x5, x14, x15, x12, x13)) of
+//      v_mfma_f32_16x16x32_f16 against the two 16-column halves of H_32,
+//      with the offset correction as the accumulator input.  |value| <= 512.
+//   4. The results are cast to fp16 (exact) and one packed-fp16 butterfly
+//      stage runs over x7 (|value| <= 1024, exact).
+//   5. Pass 2: in the result layout a lane holds rows 4 (lane / 16) + i of a
+//      16 x 16 tile, column lane mod 16, so the four results of the tiles for
+//      x6 = 0 and x6 = 1 form a new A operand whose K slots are
+//      (x8, x9, x6, x10, x11); the same H_32 halves transform them.
 //   6. |value| <= 2^15 at the end, exact in fp32; the maximum is taken with
 //      abs modifiers.
-// Every bit of x is transformed exactly once (5 + 2 + 5 + 4); which output
+// Every bit of x is transformed exactly once (5 + 5 + 1 + 5); which output
 // index lands where does not matter for the maximum.
 // ---------------------------------------------------------------------------
 typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
-typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
@@ -557,10 +562,27 @@ __device__ __forceinline__ uint32_t pkf16_sub(uint32_t a, uint32_t b) {
   return __builtin_bit_cast(uint32_t, __builtin_bit_cast(f16x2, a) - __builtin_bit_cast(f16x2, b));
 }
 __device__ __forceinline__ _Float16 hsign(int bits) { return (__builtin_popcount(bits) & 1) ? (_Float16)-1.0f : (_Float16)1.0f; }
+__device__ __forceinline__ uint32_t pk_cvt_f16(float lo, float hi) {
+  f16x2 r;
+  r[0] = (_Float16)lo;
+  r[1] = (_Float16)hi;
+  return __builtin_bit_cast(uint32_t, r);
+}
+__device__ __forceinline__ f16x8 as_f16x8(uint32_t r0, uint32_t r1, uint32_t r2, uint32_t r3) {
+  const f16x2 p0 = __builtin_bit_cast(f16x2, r0), p1 = __builtin_bit_cast(f16x2, r1);
+  const f16x2 p2 = __builtin_bit_cast(f16x2, r2), p3 = __builtin_bit_cast(f16x2, r3);
+  f16x8 v;
+  v[0] = p0[0]; v[1] = p0[1]; v[2] = p1[0]; v[3] = p1[1];
+  v[4] = p2[0]; v[5] = p2[1]; v[6] = p3[0]; v[7] = p3[1];
+  return v;
+}
 
-__global__ __launch_bounds__(kWG, 2) void k_walsh_mfma16(const KParams kp) {
+template <int ROUNDS>
+__global__ __launch_bounds__(kWG, ROUNDS) void k_walsh_mfma16(const KParams kp) {
   constexpr int NW = 8;
-  constexpr int LDSW = 16 * 4 * 4 * 64;  // one round: 16 a' x 4 (a6,a7) x 4 source waves x 64 lanes
+  constexpr int TPR = 8 / ROUNDS;              // a' & 7 values per round
+  constexpr int LDSW = 4 * TPR * 4 * 4 * 64;   // dest wave x (a' & 7) x v x source wave x lane
+  static_assert(ROUNDS == 2 || ROUNDS == 4, "rounds");
   __shared__ uint32_t lds[LDSW];
   __shared__ int red[kWG / 64];
   __shared__ long long s_item;
@@ -570,8 +592,8 @@ __global__ __launch_bounds__(kWG, 2) void k_walsh_mfma16(const KParams kp) {
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int C = kp.chunk;
 
-  // Constant B operands.  Pass 1 slot (g = lane/16, j) is the 5-bit index
-  // kappa = j + 8 g; column n = lane % 16 (+ 16 for the second half).
+  // B operands: slot (g = lane / 16, j) is the 5-bit index kappa = j + 8 g;
+  // column n = lane % 16 (+ 16 for the second half).
   f16x8 hb0, hb1;
   {
     const int g = lane >> 4, n = lane & 15;
@@ -582,12 +604,10 @@ __global__ __launch_bounds__(kWG, 2) void k_walsh_mfma16(const KParams kp) {
       hb1[j] = hsign(kappa & (n + 16));
     }
   }
-  f16x4 hc;
-  {
-    const int g = lane >> 4, n = lane & 15;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) hc[j] = hsign((j + 4 * g) & n);
-  }
+  // accumulator input of pass 1, first half: takes 32 * 1536 off column 0
+  const float fix = (lane & 15) == 0 ? -49152.0f : 0.0f;
+  const f32x4 cfix = {fix, fix, fix, fix};
+  const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
 
   for (;;) {
     if (tid == 0) s_item = (long long)atomicAdd(kp.queue, 1);
@@ -638,73 +658,74 @@ __global__ __launch_bounds__(kWG, 2) void k_walsh_mfma16(const KParams kp) {
       const bool valid = inrange && k != 0;
       const uint32_t b = (uint32_t)gray(k);
 
-      // ---- 1. popcount stages as fp16, pairs over x5
-      uint32_t R[32][4];
-      const uint32_t bias = 0x66006600u;  // fp16 1536 in both halves
+      float m0 = 0.0f, m1 = 0.0f;
 #pragma unroll
-      for (int a = 0; a < 32; ++a) {
+      for (int r = 0; r < ROUNDS; ++r) {
+        // ---- 1. popcount stages of the a' = dw * 8 + r * TPR + tt, to LDS
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const uint32_t c0 = __builtin_popcount(G[2 * v] ^ walsh_mask(a)) + (0x6600 - 16);
-          const uint32_t c1 = __builtin_popcount(G[2 * v + 1] ^ walsh_mask(a)) + (0x6600 - 16);
-          R[a][v] = pkf16_sub(__builtin_amdgcn_perm(c1, c0, 0x05040100u), bias);
-        }
-      }
-      // ---- 2. stages over x6, x7 (v bits)
+        for (int dw = 0; dw < 4; ++dw)
 #pragma unroll
-      for (int a = 0; a < 32; ++a) {
-        uint32_t t0 = pkf16_add(R[a][0], R[a][1]), t1 = pkf16_sub(R[a][0], R[a][1]);
-        uint32_t t2 = pkf16_add(R[a][2], R[a][3]), t3 = pkf16_sub(R[a][2], R[a][3]);
-        R[a][0] = pkf16_add(t0, t2);
-        R[a][2] = pkf16_sub(t0, t2);
-        R[a][1] = pkf16_add(t1, t3);
-        R[a][3] = pkf16_sub(t1, t3);
-      }
-      // ---- 3. exchange: R[a'][v] of thread (s = wave, l) -> R[a'][q = s] of thread (w = v, l)
+          for (int tt = 0; tt < TPR; ++tt) {
+            const uint32_t L = walsh_mask(dw * 8 + r * TPR + tt);
 #pragma unroll
-      for (int r = 0; r < 2; ++r) {
+            for (int v = 0; v < 4; ++v) {
+              const uint32_t c0 = __builtin_popcount(G[2 * v] ^ L) + (0x6600 - 16);
+              const uint32_t c1 = __builtin_popcount(G[2 * v + 1] ^ L) + (0x6600 - 16);
+              lds[(((dw * TPR + tt) * 4 + v) * 4 + wave) * 64 + lane] = __builtin_amdgcn_perm(c1, c0, 0x05040100u);
+            }
+          }
+        __syncthreads();
+        uint32_t R[TPR][4][4];
 #pragma unroll
-        for (int a = 0; a < 16; ++a)
+        for (int tt = 0; tt < TPR; ++tt)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) lds[((a * 4 + v) * 4 + wave) * 64 + lane] = R[r * 16 + a][v];
+          for (int v = 0; v < 4; ++v)
+#pragma unroll
+            for (int s = 0; s < 4; ++s) R[tt][v][s] = lds[(((wave * TPR + tt) * 4 + v) * 4 + s) * 64 + lane];
         __syncthreads();
 #pragma unroll
-        for (int a = 0; a < 16; ++a)
+        for (int tt = 0; tt < TPR; ++tt) {
+          // ---- 3. pass 1 per v, results to fp16: P[v][half][2]
+          uint32_t P[4][2][2];
 #pragma unroll
-          for (int q = 0; q < 4; ++q) R[r * 16 + a][q] = lds[((a * 4 + wave) * 4 + q) * 64 + lane];
-        __syncthreads();
-      }
-      // ---- 4-6. matrix-core passes and the maximum
-      float mxf = 0.0f;
+          for (int v = 0; v < 4; ++v) {
+            const f16x8 av = as_f16x8(R[tt][v][0], R[tt][v][1], R[tt][v][2], R[tt][v][3]);
+            const f32x4 d0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(av, hb0, cfix, 0, 0, 0);
+            const f32x4 d1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(av, hb1, zero, 0, 0, 0);
+            P[v][0][0] = pk_cvt_f16(d0[0], d0[1]);
+            P[v][0][1] = pk_cvt_f16(d0[2], d0[3]);
+            P[v][1][0] = pk_cvt_f16(d1[0], d1[1]);
+            P[v][1][1] = pk_cvt_f16(d1[2], d1[3]);
+          }
+          // ---- 4. stage over x7 (v = x6 + 2 x7)
 #pragma unroll
-      for (int a = 0; a < 32; ++a) {
-        f16x8 av;
+          for (int x6 = 0; x6 < 2; ++x6)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const f16x2 pr = __builtin_bit_cast(f16x2, R[a][q]);
-          av[2 * q] = pr[0];
-          av[2 * q + 1] = pr[1];
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+              for (int i = 0; i < 2; ++i) {
+                const uint32_t p = P[x6][h][i], q = P[x6 + 2][h][i];
+                P[x6][h][i] = pkf16_add(p, q);
+                P[x6 + 2][h][i] = pkf16_sub(p, q);
+              }
+          // ---- 5. pass 2 per (a7, half), 6. the maximum
+#pragma unroll
+          for (int a7 = 0; a7 < 2; ++a7)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+              const f16x8 av = as_f16x8(P[2 * a7][h][0], P[2 * a7][h][1], P[2 * a7 + 1][h][0], P[2 * a7 + 1][h][1]);
+              const f32x4 e0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(av, hb0, zero, 0, 0, 0);
+              const f32x4 e1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(av, hb1, zero, 0, 0, 0);
+              // v_max3 with abs modifiers; the compiler inserts the wait
+              // states an MFMA result needs before a VALU reads it
+              m0 = fmaxf(fmaxf(m0, fabsf(e0[0])), fabsf(e1[0]));
+              m1 = fmaxf(fmaxf(m1, fabsf(e0[1])), fabsf(e1[1]));
+              m0 = fmaxf(fmaxf(m0, fabsf(e0[2])), fabsf(e1[2]));
+              m1 = fmaxf(fmaxf(m1, fabsf(e0[3])), fabsf(e1[3]));
+            }
         }
-        const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
-        const f32x4 d0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(av, hb0, zero, 0, 0, 0);
-        const f32x4 d1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(av, hb1, zero, 0, 0, 0);
-        f16x4 a0, a1;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          a0[j] = (_Float16)d0[j];
-          a1[j] = (_Float16)d1[j];
-        }
-        const f32x4 e0 = __builtin_amdgcn_mfma_f32_16x16x16f16(a0, hc, zero, 0, 0, 0);
-        const f32x4 e1 = __builtin_amdgcn_mfma_f32_16x16x16f16(a1, hc, zero, 0, 0, 0);
-        // pairwise |.| maxima, then into the running maximum (v_max with abs
-        // modifiers, then v_max3); the compiler inserts the wait states an
-        // MFMA result needs before a VALU reads it
-        const float p0 = fmaxf(fabsf(e0[0]), fabsf(e1[0])), p1 = fmaxf(fabsf(e0[1]), fabsf(e1[1]));
-        const float p2 = fmaxf(fabsf(e0[2]), fabsf(e1[2])), p3 = fmaxf(fabsf(e0[3]), fabsf(e1[3]));
-        mxf = fmaxf(fmaxf(mxf, p0), p1);
-        mxf = fmaxf(fmaxf(mxf, p2), p3);
       }
-      int mx = (int)mxf;
+      int mx = (int)fmaxf(m0, m1);
 #pragma unroll
       for (int o = 1; o < 64; o <<= 1) mx = max(mx, __shfl_xor(mx, o, 64));
       if (lane == 0) red[wave] = mx;
