@@ -584,7 +584,7 @@ __global__ __launch_bounds__(kWG, ROUNDS) void k_walsh_mfma16(const KParams kp) 
   constexpr int LDSW = 4 * TPR * 4 * 4 * 64;   // dest wave x (a' & 7) x v x source wave x lane
   static_assert(ROUNDS == 2 || ROUNDS == 4, "rounds");
   __shared__ uint32_t lds[LDSW];
-  __shared__ int red[kWG / 64];
+  __shared__ int red[64 * 4];  // per mask of a run of 64: the 4 wave maxima
   __shared__ long long s_item;
 
   const int tid = threadIdx.x;
@@ -655,12 +655,10 @@ __global__ __launch_bounds__(kWG, ROUNDS) void k_walsh_mfma16(const KParams kp) 
         const int i = __builtin_ctzll((unsigned long long)(k + 1));
         load_words<NW>(Fn, jd.F + (long long)i * jd.nwords + wb, false);
       }
-      const bool valid = inrange && k != 0;
-      const uint32_t b = (uint32_t)gray(k);
-
       float m0 = 0.0f, m1 = 0.0f;
 #pragma unroll
       for (int r = 0; r < ROUNDS; ++r) {
+
         // ---- 1. popcount stages of the a' = dw * 8 + r * TPR + tt, to LDS
 #pragma unroll
         for (int dw = 0; dw < 4; ++dw)
@@ -728,12 +726,27 @@ __global__ __launch_bounds__(kWG, ROUNDS) void k_walsh_mfma16(const KParams kp) 
       int mx = (int)fmaxf(m0, m1);
 #pragma unroll
       for (int o = 1; o < 64; o <<= 1) mx = max(mx, __shfl_xor(mx, o, 64));
-      if (lane == 0) red[wave] = mx;
-      __syncthreads();
-      mx = max(max(red[0], red[1]), max(red[2], red[3]));
-      if (tid == 0 && valid) {
-        if (jd.maxabs) jd.maxabs[b] = 2 * mx;
-        runmin = min(runmin, (1 << (n - 1)) - mx);
+      if (lane == 0) red[(step & 63) * 4 + wave] = mx;
+      if ((step & 63) == 63 || step == C - 1) {
+        // every 64 masks and at the item's end: wave 0 finishes the masks
+        // kfirst + s0 .. kfirst + step, one per lane
+        __syncthreads();
+        if (wave == 0) {
+          const long long s0 = step & ~63LL;
+          const long long kk = kfirst + s0 + lane;
+          int v = 0x7fffffff;
+          if (s0 + lane <= step && kk < kend && kk != 0) {
+            const int* pr = red + lane * 4;
+            const int pm = max(max(pr[0], pr[1]), max(pr[2], pr[3]));
+            if (jd.maxabs) jd.maxabs[(uint32_t)gray(kk)] = 2 * pm;
+            v = (1 << (n - 1)) - pm;
+          }
+#pragma unroll
+          for (int o = 1; o < 64; o <<= 1) v = min(v, __shfl_xor(v, o, 64));
+          runmin = min(runmin, v);
+        }
+        // no second barrier: red is next written after the next round's
+        // first barrier, which wave 0 reaches only after these reads
       }
     }
     if (tid == 0 && runmin != 0x7fffffff) atomicMin(jd.nl, runmin);
