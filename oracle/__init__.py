@@ -63,6 +63,11 @@ def _load():
         lib.oracle_criteria.restype = ctypes.c_int
         lib.oracle_autocorrelation.argtypes = [u32p, ctypes.c_int, ctypes.c_int, ctypes.c_uint32, i32p]
         lib.oracle_autocorrelation.restype = ctypes.c_int
+        lib.oracle_walsh_histogram.argtypes = [u32p, ctypes.c_int, ctypes.c_int,
+                                               ctypes.POINTER(ctypes.c_uint64), ctypes.c_int]
+        lib.oracle_walsh_histogram.restype = ctypes.c_int
+        lib.oracle_avalanche.argtypes = [u32p, ctypes.c_int, ctypes.c_int, i32p, i32p, ctypes.c_int]
+        lib.oracle_avalanche.restype = ctypes.c_int
         for f in (lib.oracle_walsh_nl, lib.oracle_walsh_maxabs_masks, lib.oracle_spectrum,
                   lib.oracle_nl_from_spectrum, lib.oracle_walsh_column):
             f.restype = ctypes.c_int
@@ -178,3 +183,33 @@ def autocorrelation(S, n: int, m: int, b: int) -> np.ndarray:
     if rc != 0:
         raise ValueError("oracle_autocorrelation rejected its arguments")
     return r
+
+
+def walsh_histogram(S, n: int, m: int, nthreads: int = 1) -> np.ndarray:
+    """hist[k] = #{(a, b): b != 0, |W(a, b)| = 2k}, k = 0 .. 2^(n-1) (uint64)."""
+    lib = _load()
+    t = _table(S, n)
+    h = np.zeros((1 << (n - 1)) + 1, dtype=np.uint64)
+    rc = lib.oracle_walsh_histogram(_p(t, ctypes.c_uint32), n, m, _p(h, ctypes.c_uint64), int(nthreads))
+    if rc != 0:
+        raise ValueError("oracle_walsh_histogram rejected its arguments")
+    return h
+
+
+AVALANCHE_FIELDS = ("sac_max", "bic_sac_max", "bic_nl")
+
+
+def avalanche(S, n: int, m: int, full: bool = True, nthreads: int = 1):
+    """Unit-difference autocorrelations and the avalanche / bit-independence summary.
+
+    Returns (summary dict, r) with r of shape (n, 2^m) (None when full is False:
+    then only the entries the summary needs are summed)."""
+    lib = _load()
+    t = _table(S, n)
+    r = np.empty((n, 1 << m), dtype=np.int32) if full else None
+    summ = np.zeros(3, dtype=np.int32)
+    rc = lib.oracle_avalanche(_p(t, ctypes.c_uint32), n, m, _p(r, ctypes.c_int32) if full else None,
+                              _p(summ, ctypes.c_int32), int(nthreads))
+    if rc != 0:
+        raise ValueError("oracle_avalanche rejected its arguments")
+    return {k: int(summ[i]) for i, k in enumerate(AVALANCHE_FIELDS)}, r

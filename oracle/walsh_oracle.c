@@ -326,3 +326,111 @@ int oracle_autocorrelation(const uint32_t* S, int n, int m, uint32_t b, int32_t*
     }
     return 0;
 }
+
+/*
+ * Histogram of |W| over the nonzero masks: the distribution of the entries
+ * of the Walsh matrix of Section 3, Eq. 1 (equivalently of the linear
+ * approximation table W/2), columns b = 1 .. 2^m - 1 as in Eq. 3:
+ *   hist[k] = #{(a, b) : b != 0, |W(a, b)| = 2k},   k = 0 .. 2^(n-1).
+ * One transform per mask as in Algorithm 1, then a count; threads split the
+ * masks and their private counts are added at the end.
+ */
+int oracle_walsh_histogram(const uint32_t* S, int n, int m, uint64_t* hist, int nthreads) {
+    if (!S || !hist || !valid_nm(n, m) || n > 20) return -1;
+    const uint32_t N = 1u << n;
+    const uint32_t NB = (N >> 1) + 1u;
+    const int64_t M = (int64_t)1 << m;
+    int failed = 0;
+    if (nthreads < 1) nthreads = 1;
+    memset(hist, 0, sizeof(uint64_t) * NB);
+#pragma omp parallel num_threads(nthreads) reduction(| : failed)
+    {
+        int32_t* f = (int32_t*)malloc(sizeof(int32_t) * N);
+        uint64_t* h = (uint64_t*)calloc(NB, sizeof(uint64_t));
+        if (!f || !h) {
+            failed = 1;
+        } else {
+#pragma omp for schedule(dynamic, 1)
+            for (int64_t b = 1; b < M; ++b) {
+                polarity_column(S, n, (uint32_t)b, f);
+                fwht_inplace(f, n);
+                for (uint32_t a = 0; a < N; ++a) {
+                    const int32_t w = f[a] < 0 ? -f[a] : f[a];
+                    h[(uint32_t)w >> 1] += 1;
+                }
+            }
+#pragma omp critical
+            for (uint32_t k = 0; k < NB; ++k) hist[k] += h[k];
+        }
+        free(f);
+        free(h);
+    }
+    return failed ? -1 : 0;
+}
+
+/* r_b(e_i) = sum_x (-1)^parity(b & (S[x] ^ S[x ^ e_i])), from the definition. */
+static int32_t unit_autocorrelation(const uint32_t* S, int n, uint32_t mmask, int i, uint32_t b) {
+    const uint32_t N = 1u << n;
+    int32_t acc = 0;
+    for (uint32_t x = 0; x < N; ++x) acc += parity32(b & (S[x] ^ S[x ^ (1u << i)]) & mmask) ? -1 : 1;
+    return acc;
+}
+
+/*
+ * Avalanche and bit independence (criteria named as future work in
+ * Section 7), from the autocorrelation of the components at the unit input
+ * differences e_i = 2^i:
+ *   r[i * 2^m + b] = sum_x (-1)^parity(b & (S[x] ^ S[x ^ e_i])),  i < n, b < 2^m,
+ * summed from its definition (all of it when r is given; otherwise only the
+ * entries the summary needs).  Flipping input bit i flips the component of
+ * mask b with probability (1 - r / 2^n) / 2.  summary[0..2]:
+ *   [0] max_{i, j} |r_{e_j}(e_i)|: strict avalanche of each output bit
+ *       (0 when every output bit flips with probability exactly 1/2);
+ *   [1] max_{i, j < k} |r_{e_j ^ e_k}(e_i)|: the same for the XOR of two output
+ *       bits, the avalanche half of bit independence (-1 if m < 2);
+ *   [2] min_{j < k} NL(x -> bit j of S(x) XOR bit k of S(x)), each from its own
+ *       transform (Eq. 3 for one mask): the nonlinearity half of bit
+ *       independence (-1 if m < 2).
+ */
+int oracle_avalanche(const uint32_t* S, int n, int m, int32_t* r, int32_t* summary, int nthreads) {
+    if (!S || !summary || !valid_nm(n, m) || n > 16 || m > 16) return -1;
+    const uint32_t N = 1u << n;
+    const uint32_t M = 1u << m;
+    const uint32_t mmask = M - 1u;
+    if (nthreads < 1) nthreads = 1;
+    if (r) {
+#pragma omp parallel for num_threads(nthreads) schedule(dynamic, 1) collapse(2)
+        for (int i = 0; i < n; ++i)
+            for (int64_t b = 0; b < (int64_t)M; ++b)
+                r[(size_t)i * M + (uint32_t)b] = unit_autocorrelation(S, n, mmask, i, (uint32_t)b);
+    }
+    int32_t sac = 0, bic = m >= 2 ? 0 : -1, bicnl = m >= 2 ? (int32_t)(N >> 1) : -1;
+#pragma omp parallel for num_threads(nthreads) schedule(dynamic, 1) reduction(max : sac, bic)
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < m; ++j) {
+            const uint32_t bj = 1u << j;
+            const int32_t v = r ? r[(size_t)i * M + bj] : unit_autocorrelation(S, n, mmask, i, bj);
+            if ((v < 0 ? -v : v) > sac) sac = v < 0 ? -v : v;
+            for (int k = j + 1; k < m; ++k) {
+                const uint32_t bjk = bj | (1u << k);
+                const int32_t u = r ? r[(size_t)i * M + bjk] : unit_autocorrelation(S, n, mmask, i, bjk);
+                if ((u < 0 ? -u : u) > bic) bic = u < 0 ? -u : u;
+            }
+        }
+    if (m >= 2) {
+        int32_t* f = (int32_t*)malloc(sizeof(int32_t) * N);
+        if (!f) return -1;
+        for (int j = 0; j < m; ++j)
+            for (int k = j + 1; k < m; ++k) {
+                polarity_column(S, n, (1u << j) | (1u << k), f);
+                fwht_inplace(f, n);
+                const int32_t nlb = ((int32_t)N - max_abs(f, N)) >> 1;
+                if (nlb < bicnl) bicnl = nlb;
+            }
+        free(f);
+    }
+    summary[0] = sac;
+    summary[1] = bic;
+    summary[2] = bicnl;
+    return 0;
+}
