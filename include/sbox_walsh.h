@@ -194,6 +194,52 @@ sbox_status sbox_criteria(const void* S, int n, int m, int s_elem_bytes, int32_t
                           int32_t* w0_per_b, int32_t* minwt_per_b, int32_t* acmax_per_b,
                           int32_t* pcwt_per_b, void* stream);
 
+/*
+ * Histogram of |W| over the nonzero masks: the distribution of the entries
+ * of the Walsh matrix of Eq. 1 (equivalently of the linear approximation
+ * table W/2), counted inside the transform, so the matrix is never stored:
+ *   hist[k] = #{(a, b) : 1 <= b < 2^m, |W(a, b)| = 2k},   k = 0 .. 2^(n-1).
+ *   hist          device uint64[2^(n-1) + 1], overwritten (no need to clear it).
+ *   maxabs_per_b  device int32[2^m] or NULL; nl device int32[1] or NULL: the
+ *                 fused per-mask maximum and NL of the same pass.
+ *   workspace     at least sbox_walsh_histogram_workspace_bytes(n, m) bytes.
+ * Limits: 1 <= n <= 16, 1 <= m <= 24.  No allocation, no host
+ * synchronisation.  About as costly as a spectrum pass without its stores.
+ */
+sbox_status sbox_walsh_histogram(const void* S, int n, int m, int s_elem_bytes, uint64_t* hist,
+                                 int32_t* maxabs_per_b, int32_t* nl, void* workspace,
+                                 size_t workspace_bytes, void* stream);
+size_t sbox_walsh_histogram_workspace_bytes(int n, int m);
+
+/*
+ * Strict avalanche and bit independence (more of the paper's future work,
+ * Section 7), from the autocorrelation of every component at the unit input
+ * differences e_i = 2^i:
+ *   r[i * 2^m + b] = sum_x (-1)^parity(b & (S[x] ^ S[x ^ e_i])),  i < n, b < 2^m,
+ * computed as the 2^m-point Walsh-Hadamard transform over the output masks
+ * of the counts #{x : S[x] ^ S[x ^ e_i] = y}.  Flipping input bit i flips the
+ * component of mask b with probability (1 - r / 2^n) / 2.
+ *   r             device int32[n * 2^m], or NULL (then the workspace holds it).
+ *   summary       device int32[3] (required):
+ *                 [0] max_{i,j} |r_{e_j}(e_i)|: 0 iff every output bit
+ *                     satisfies the strict avalanche criterion;
+ *                 [1] max_{i, j<k} |r_{e_j ^ e_k}(e_i)|: the same for every XOR
+ *                     of two output bits (bit independence), -1 if m < 2;
+ *                 [2] min_{j<k} of the NL of the XOR of output bits j and k
+ *                     (bit-independence nonlinearity) read from maxabs_per_b,
+ *                     -1 if maxabs_per_b is NULL or m < 2.
+ *   maxabs_per_b  device int32[2^m] written by sbox_walsh_nl(_ex) for the
+ *                 same box (read only), or NULL.
+ *   workspace     at least sbox_avalanche_workspace_bytes(n, m) bytes when r
+ *                 is NULL; unused (may be NULL) otherwise.
+ * Limits: 1 <= n <= 24, 1 <= m <= 20, n + m <= 40.  No allocation, no host
+ * synchronisation.
+ */
+sbox_status sbox_avalanche(const void* S, int n, int m, int s_elem_bytes, int32_t* r, int32_t* summary,
+                           const int32_t* maxabs_per_b, void* workspace, size_t workspace_bytes,
+                           void* stream);
+size_t sbox_avalanche_workspace_bytes(int n, int m);
+
 /* Text describing the last non-OK status returned on this thread ("" if none). */
 const char* sbox_last_error(void);
 

@@ -68,6 +68,9 @@ def _load():
         lib.oracle_walsh_histogram.restype = ctypes.c_int
         lib.oracle_avalanche.argtypes = [u32p, ctypes.c_int, ctypes.c_int, i32p, i32p, ctypes.c_int]
         lib.oracle_avalanche.restype = ctypes.c_int
+        lib.oracle_unit_autocorrelation_masks.argtypes = [u32p, ctypes.c_int, ctypes.c_int, u32p, ctypes.c_int64,
+                                                          i32p, ctypes.c_int]
+        lib.oracle_unit_autocorrelation_masks.restype = ctypes.c_int
         for f in (lib.oracle_walsh_nl, lib.oracle_walsh_maxabs_masks, lib.oracle_spectrum,
                   lib.oracle_nl_from_spectrum, lib.oracle_walsh_column):
             f.restype = ctypes.c_int
@@ -213,3 +216,16 @@ def avalanche(S, n: int, m: int, full: bool = True, nthreads: int = 1):
     if rc != 0:
         raise ValueError("oracle_avalanche rejected its arguments")
     return {k: int(summ[i]) for i, k in enumerate(AVALANCHE_FIELDS)}, r
+
+
+def unit_autocorrelation_masks(S, n: int, m: int, masks, nthreads: int = 1) -> np.ndarray:
+    """r[i, j] = r_{masks[j]}(e_i) from the definition, for a sample of masks (n <= 20)."""
+    lib = _load()
+    t = _table(S, n)
+    bs = np.ascontiguousarray(np.asarray(masks, dtype=np.uint32))
+    r = np.empty((n, bs.size), dtype=np.int32)
+    rc = lib.oracle_unit_autocorrelation_masks(_p(t, ctypes.c_uint32), n, m, _p(bs, ctypes.c_uint32), bs.size,
+                                               _p(r, ctypes.c_int32), int(nthreads))
+    if rc != 0:
+        raise ValueError("oracle_unit_autocorrelation_masks rejected its arguments")
+    return r

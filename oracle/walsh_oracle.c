@@ -434,3 +434,15 @@ int oracle_avalanche(const uint32_t* S, int n, int m, int32_t* r, int32_t* summa
     summary[2] = bicnl;
     return 0;
 }
+
+/* r[i * count + j] = r_{bs[j]}(e_i) for i < n, from the definition (a sample of masks). */
+int oracle_unit_autocorrelation_masks(const uint32_t* S, int n, int m, const uint32_t* bs, int64_t count,
+                                      int32_t* r, int nthreads) {
+    if (!S || !bs || !r || !valid_nm(n, m) || n > 20 || count < 0) return -1;
+    const uint32_t mmask = (m >= 32) ? 0xffffffffu : ((1u << m) - 1u);
+    if (nthreads < 1) nthreads = 1;
+#pragma omp parallel for num_threads(nthreads) schedule(dynamic, 1) collapse(2)
+    for (int i = 0; i < n; ++i)
+        for (int64_t j = 0; j < count; ++j) r[(size_t)i * count + j] = unit_autocorrelation(S, n, mmask, i, bs[j]);
+    return 0;
+}

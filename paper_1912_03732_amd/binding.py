@@ -55,7 +55,9 @@ class sbox_job(ctypes.Structure):
 # Every exported symbol of include/sbox_walsh.h.
 EXPORTS = ("sbox_walsh_nl", "sbox_walsh_nl_ex", "sbox_walsh_nl_workspace_bytes",
            "sbox_walsh_nl_batched", "sbox_batched_workspace_bytes", "sbox_plan_create",
-           "sbox_plan_launch", "sbox_plan_destroy", "sbox_criteria", "sbox_last_error", "sbox_version")
+           "sbox_plan_launch", "sbox_plan_destroy", "sbox_criteria", "sbox_walsh_histogram",
+           "sbox_walsh_histogram_workspace_bytes", "sbox_avalanche", "sbox_avalanche_workspace_bytes",
+           "sbox_last_error", "sbox_version")
 
 _lib = None
 
@@ -84,6 +86,14 @@ def load(path: str = LIB_PATH):
     lib.sbox_plan_destroy.restype = None
     lib.sbox_criteria.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, vp, vp]
     lib.sbox_criteria.restype = ctypes.c_int
+    lib.sbox_walsh_histogram.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, sz, vp]
+    lib.sbox_walsh_histogram.restype = ctypes.c_int
+    lib.sbox_walsh_histogram_workspace_bytes.argtypes = [i32, i32]
+    lib.sbox_walsh_histogram_workspace_bytes.restype = sz
+    lib.sbox_avalanche.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, sz, vp]
+    lib.sbox_avalanche.restype = ctypes.c_int
+    lib.sbox_avalanche_workspace_bytes.argtypes = [i32, i32]
+    lib.sbox_avalanche_workspace_bytes.restype = sz
     lib.sbox_last_error.restype = ctypes.c_char_p
     lib.sbox_version.restype = ctypes.c_char_p
     for f in ("sbox_walsh_nl", "sbox_walsh_nl_ex", "sbox_walsh_nl_batched", "sbox_plan_create",
@@ -147,6 +157,26 @@ def sbox_criteria(S: int, n: int, m: int, s_elem_bytes: int, summary: int, w0_pe
                   minwt_per_b: int, acmax_per_b: int, pcwt_per_b: int, stream: int) -> int:
     return load().sbox_criteria(S, n, m, s_elem_bytes, summary, w0_per_b, minwt_per_b, acmax_per_b,
                                 pcwt_per_b, stream)
+
+
+def sbox_walsh_histogram(S: int, n: int, m: int, s_elem_bytes: int, hist: int, maxabs_per_b: int, nl: int,
+                         workspace: int, workspace_bytes: int, stream: int) -> int:
+    return load().sbox_walsh_histogram(S, n, m, s_elem_bytes, hist, maxabs_per_b, nl, workspace,
+                                       workspace_bytes, stream)
+
+
+def sbox_walsh_histogram_workspace_bytes(n: int, m: int) -> int:
+    return int(load().sbox_walsh_histogram_workspace_bytes(n, m))
+
+
+def sbox_avalanche(S: int, n: int, m: int, s_elem_bytes: int, r: int, summary: int, maxabs_per_b: int,
+                   workspace: int, workspace_bytes: int, stream: int) -> int:
+    return load().sbox_avalanche(S, n, m, s_elem_bytes, r, summary, maxabs_per_b, workspace,
+                                 workspace_bytes, stream)
+
+
+def sbox_avalanche_workspace_bytes(n: int, m: int) -> int:
+    return int(load().sbox_avalanche_workspace_bytes(n, m))
 
 
 def sbox_last_error() -> str:
@@ -333,3 +363,44 @@ def criteria(S, n: int, m: int, *, per_mask: bool = True, stream=None):
     torch.cuda.synchronize(dev)
     v = summ.cpu().tolist()
     return {k: int(v[i]) for i, k in enumerate(CRITERIA_FIELDS)}, arrs
+
+
+def walsh_histogram(S, n: int, m: int, *, maxabs: bool = False, stream=None):
+    """|W| histogram over the nonzero masks: hist[k] = #{(a, b): b != 0,
+    |W(a, b)| = 2k} as an int64 device tensor of 2^(n-1) + 1 counts, with
+    (nl, maxabs tensor or None) from the same pass."""
+    torch = _torch()
+    if not isinstance(S, torch.Tensor) or not S.is_cuda:
+        raise TypeError("S must be a device tensor")
+    S = S.contiguous()
+    dev = S.device
+    hist = torch.empty((1 << (n - 1)) + 1, dtype=torch.int64, device=dev)
+    nl = torch.empty(1, dtype=torch.int32, device=dev)
+    mx = torch.empty(1 << m, dtype=torch.int32, device=dev) if maxabs else None
+    ws = Workspace(sbox_walsh_histogram_workspace_bytes(n, m), dev)
+    _check(sbox_walsh_histogram(S.data_ptr(), n, m, S.element_size(), hist.data_ptr(),
+                                mx.data_ptr() if mx is not None else 0, nl.data_ptr(), ws.ptr, ws.nbytes,
+                                _stream(torch, stream)))
+    torch.cuda.synchronize(dev)
+    return hist, int(nl.item()), mx
+
+
+AVALANCHE_FIELDS = ("sac_max", "bic_sac_max", "bic_nl")
+
+
+def avalanche(S, n: int, m: int, *, maxabs=None, stream=None):
+    """Unit-difference autocorrelations r (an (n, 2^m) int32 device tensor)
+    and the strict-avalanche / bit-independence summary; pass the maxabs
+    tensor of walsh_nl on the same box to get the bit-independence NL."""
+    torch = _torch()
+    if not isinstance(S, torch.Tensor) or not S.is_cuda:
+        raise TypeError("S must be a device tensor")
+    S = S.contiguous()
+    dev = S.device
+    r = torch.empty((n, 1 << m), dtype=torch.int32, device=dev)
+    summ = torch.empty(3, dtype=torch.int32, device=dev)
+    _check(sbox_avalanche(S.data_ptr(), n, m, S.element_size(), r.data_ptr(), summ.data_ptr(),
+                          maxabs.data_ptr() if maxabs is not None else 0, 0, 0, _stream(torch, stream)))
+    torch.cuda.synchronize(dev)
+    v = summ.cpu().tolist()
+    return {k: int(v[i]) for i, k in enumerate(AVALANCHE_FIELDS)}, r

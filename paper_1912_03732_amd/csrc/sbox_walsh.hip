@@ -44,12 +44,7 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 // ------------------------------------------------------------- kernels ----
 using KFn = void (*)(KParams);
 
-int default_split(int n) {
-  if (n <= 8) return n;
-  if (n <= 12) return 6;
-  if (n <= 14) return 7;
-  return 8;
-}
+constexpr int default_split(int n) { return n <= 8 ? n : (n <= 12 ? 6 : (n <= 14 ? 7 : 8)); }
 
 bool split_valid(int n, int p) {
   if (n <= 8) return p == n;
@@ -59,9 +54,13 @@ bool split_valid(int n, int p) {
 template <int N, int P>
 KFn pick_mode(int mode, bool any_p) {
   if (mode == kMax) return &k_walsh<N, P, kMax>;
-  if (any_p) return nullptr;  // store modes exist for the default split only
-  if (mode == kStoreB) return &k_walsh<N, P, kStoreB>;
-  if (mode == kStoreA) return &k_walsh<N, P, kStoreA>;
+  if constexpr (P == default_split(N)) {  // the other modes exist for the default split only
+    if (any_p) return nullptr;
+    if (mode == kStoreB) return &k_walsh<N, P, kStoreB>;
+    if (mode == kStoreA) return &k_walsh<N, P, kStoreA>;
+    if (mode == kHist) return &k_walsh<N, P, kHist>;
+    if (mode == kHistBig) return &k_walsh<N, P, kHistBig>;
+  }
   return nullptr;
 }
 
@@ -285,7 +284,8 @@ sbox_status run_big(const void* S, int n, int m, int eb, int32_t* maxabs, int32_
 
 // ------------------------------------------------------- one S-box call ----
 sbox_status run_single(const void* S, int n, int m, int eb, int32_t* maxabs, int32_t* nl, int32_t* spec,
-                       int layout_arg, void* ws, size_t ws_bytes, const sbox_tuning* tun, hipStream_t st) {
+                       int layout_arg, void* ws, size_t ws_bytes, const sbox_tuning* tun, hipStream_t st,
+                       unsigned long long* hist = nullptr, unsigned long long* hist_over = nullptr) {
   const int layout = base_layout(layout_arg);
   const int wscale = wscale_of(layout_arg);
   int cus = 0;
@@ -397,7 +397,7 @@ sbox_status run_single(const void* S, int n, int m, int eb, int32_t* maxabs, int
     return SBOX_OK;
   }
 
-  if (n == 16 && layout == 0 && use_mfma16(tun)) {
+  if (n == 16 && layout == 0 && !hist && use_mfma16(tun)) {
     const void* fn = (const void*)&k_walsh_mfma16<kMfmaRounds>;
     int occ = 1;
     s = occupancy(fn, &occ);
@@ -419,7 +419,7 @@ sbox_status run_single(const void* S, int n, int m, int eb, int32_t* maxabs, int
 
   if (n <= 16) {
     const int p = (tun && tun->split_p) ? tun->split_p : default_split(n);
-    const int mode = mode_of(layout);
+    const int mode = hist ? (int)kHist : mode_of(layout);
     if (n > 8 && !split_valid(n, p)) return fail(SBOX_ERR_INVALID_ARG, "split_p=%d invalid for n=%d", p, n);
     KFn fn = lookup_kernel(n, n <= 8 ? n : p, mode);
     if (!fn) return fail(SBOX_ERR_INVALID_ARG, "no kernel for n=%d split_p=%d layout=%d", n, p, layout);
@@ -440,9 +440,22 @@ sbox_status run_single(const void* S, int n, int m, int eb, int32_t* maxabs, int
     kp.chunk = chunk;
     kp.queue = queue;
     kp.total_items = (M + per_item - 1) / per_item;
+    kp.hist = hist;
+    kp.hist_over = hist_over;
     const int grid = (int)std::min<long long>(grid_cap, kp.total_items);
     void* args[] = {&kp};
-    return launch((const void*)fn, dim3(grid), dim3(kWG), args, st);
+    s = launch((const void*)fn, dim3(grid), dim3(kWG), args, st);
+    if (s || !hist) return s;
+    // the pass for |W|/2 >= kHistBins - 1 (returns at once when there is none)
+    KFn fnb = lookup_kernel(n, n <= 8 ? n : p, kHistBig);
+    if (!fnb) return fail(SBOX_ERR_INVALID_ARG, "no histogram kernel for n=%d", n);
+    int occb = 1;
+    s = occupancy((const void*)fnb, &occb);
+    if (s) return s;
+    kp.queue = queue + 1;
+    const int gridb = (int)std::min<long long>((long long)occb * cus, kp.total_items);
+    void* argsb[] = {&kp};
+    return launch((const void*)fnb, dim3(gridb), dim3(kWG), argsb, st);
   }
 
   // ---- n > 16: 2^16-point block transforms, then the block-index stages
@@ -755,6 +768,102 @@ sbox_status sbox_walsh_nl_ex(const void* S, int n, int m, int s_elem_bytes, int3
                 large_bytes(n, m, 1));
   return run_single(S, n, m, s_elem_bytes, maxabs_per_b, nl, spectrum, layout, workspace, workspace_bytes,
                     tuning, reinterpret_cast<hipStream_t>(stream));
+}
+
+size_t sbox_walsh_histogram_workspace_bytes(int n, int m) {
+  if (n < 1 || n > 16 || m < 1 || m > 24) return 0;
+  return sbox_walsh_nl_workspace_bytes(n, m, 0) + 256;  // + the large-value count and an NL slot
+}
+
+sbox_status sbox_walsh_histogram(const void* S, int n, int m, int s_elem_bytes, uint64_t* hist,
+                                 int32_t* maxabs_per_b, int32_t* nl, void* workspace, size_t workspace_bytes,
+                                 void* stream) {
+  sbox_status s = check_nm(n, m);
+  if (s) return s;
+  if (n > 16) return fail(SBOX_ERR_UNSUPPORTED, "the |W| histogram needs n <= 16 (n=%d)", n);
+  if (!S || !hist) return fail(SBOX_ERR_INVALID_ARG, "S or hist is null");
+  if (s_elem_bytes != 1 && s_elem_bytes != 2 && s_elem_bytes != 4)
+    return fail(SBOX_ERR_INVALID_ARG, "s_elem_bytes must be 1, 2 or 4 (got %d)", s_elem_bytes);
+  const size_t need = sbox_walsh_histogram_workspace_bytes(n, m);
+  if (!workspace) return fail(SBOX_ERR_WORKSPACE, "workspace is null (need %zu bytes)", need);
+  if (reinterpret_cast<uintptr_t>(workspace) & 255) return fail(SBOX_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+  if (workspace_bytes < need) return fail(SBOX_ERR_WORKSPACE, "workspace of %zu bytes, need %zu", workspace_bytes, need);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  char* tail = reinterpret_cast<char*>(workspace) + need - 256;
+  unsigned long long* over = reinterpret_cast<unsigned long long*>(tail);
+  int32_t* nlp = nl ? nl : reinterpret_cast<int32_t*>(tail + 8);
+  for (int z = 0; z < 2; ++z) {
+    int* h = z ? reinterpret_cast<int*>(over) : reinterpret_cast<int*>(hist);
+    long long cnt = z ? 2 : 2 * ((1LL << (n - 1)) + 1);
+    void* args[] = {&h, &cnt};
+    s = launch((const void*)&k_zero, dim3(64), dim3(256), args, st);
+    if (s) return s;
+  }
+  return run_single(S, n, m, s_elem_bytes, maxabs_per_b, nlp, nullptr, 0, workspace, workspace_bytes, nullptr, st,
+                    reinterpret_cast<unsigned long long*>(hist), over);
+}
+
+size_t sbox_avalanche_workspace_bytes(int n, int m) {
+  if (n < 1 || n > 24 || m < 1 || m > 20 || n + m > 40) return 0;
+  return align256((size_t)n << m << 2);
+}
+
+sbox_status sbox_avalanche(const void* S, int n, int m, int s_elem_bytes, int32_t* r, int32_t* summary,
+                           const int32_t* maxabs_per_b, void* workspace, size_t workspace_bytes, void* stream) {
+  if (n < 1 || n > 24 || m < 1 || m > 20 || n + m > 40)
+    return fail(SBOX_ERR_UNSUPPORTED, "avalanche needs 1 <= n <= 24, 1 <= m <= 20, n + m <= 40 (n=%d m=%d)", n, m);
+  if (!S || !summary) return fail(SBOX_ERR_INVALID_ARG, "S or summary is null");
+  if (s_elem_bytes != 1 && s_elem_bytes != 2 && s_elem_bytes != 4)
+    return fail(SBOX_ERR_INVALID_ARG, "s_elem_bytes must be 1, 2 or 4 (got %d)", s_elem_bytes);
+  int32_t* buf = r;
+  if (!buf) {
+    const size_t need = sbox_avalanche_workspace_bytes(n, m);
+    if (!workspace) return fail(SBOX_ERR_WORKSPACE, "workspace is null (need %zu bytes without r)", need);
+    if (reinterpret_cast<uintptr_t>(workspace) & 255) return fail(SBOX_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+    if (workspace_bytes < need) return fail(SBOX_ERR_WORKSPACE, "workspace of %zu bytes, need %zu", workspace_bytes, need);
+    buf = reinterpret_cast<int32_t*>(workspace);
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const long long total = (long long)n << m;
+  sbox_status s;
+  {
+    int* b = buf;
+    long long cnt = total;
+    void* args[] = {&b, &cnt};
+    s = launch((const void*)&k_zero, dim3((unsigned)std::min<long long>(1024, (total + 255) / 256)), dim3(256), args, st);
+    if (s) return s;
+  }
+  {
+    const void* S_ = S;
+    int n_ = n, m_ = m;
+    int32_t* c = buf;
+    void* args[] = {(void*)&S_, &n_, &m_, &c};
+    const void* fn = s_elem_bytes == 1 ? (const void*)&k_deriv_count<1>
+                   : s_elem_bytes == 2 ? (const void*)&k_deriv_count<2> : (const void*)&k_deriv_count<4>;
+    const long long threads = (long long)n << (n - 1);
+    s = launch(fn, dim3((unsigned)std::min<long long>(4096, (threads + 255) / 256)), dim3(256), args, st);
+    if (s) return s;
+  }
+  // the 2^m-point transforms, in passes of at most 12 bits
+  for (int lo = 0; lo < m;) {
+    const int cwlog = std::min(lo, 6);
+    const int R = std::min(m - lo, 12 - cwlog);
+    int32_t* d = buf;
+    int mlog = m, lo_ = lo, R_ = R, cw = cwlog;
+    void* args[] = {&d, &mlog, &lo_, &R_, &cw};
+    const long long blocks = (long long)n << (m - R - cwlog);
+    s = launch((const void*)&k_fwht_pass, dim3((unsigned)blocks), dim3(256), args, st);
+    if (s) return s;
+    lo += R;
+  }
+  {
+    const int32_t* rr = buf;
+    int n_ = n, m_ = m;
+    const int32_t* mx = maxabs_per_b;
+    int32_t* sm = summary;
+    void* args[] = {(void*)&rr, &n_, &m_, (void*)&mx, &sm};
+    return launch((const void*)&k_avalanche_summary, dim3(1), dim3(256), args, st);
+  }
 }
 
 sbox_status sbox_walsh_nl(const void* S, int n, int m, int32_t* maxabs_per_b, int32_t* nl, void* stream) {

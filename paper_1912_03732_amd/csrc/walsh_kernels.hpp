@@ -49,7 +49,14 @@ namespace sbw {
 
 constexpr int kWG = 256;  // threads per workgroup (4 waves)
 
-enum Mode : int { kMax = 0, kStoreB = 1, kStoreA = 2, kBlock = 3 };
+enum Mode : int { kMax = 0, kStoreB = 1, kStoreA = 2, kBlock = 3, kHist = 4, kHistBig = 5 };
+
+// |W| histogram: kHist counts the bins |W|/2 < kHistBins - 1 in LDS per
+// workgroup and only the number of larger values in the last LDS bin (no
+// data-dependent branch per value); if that number is not zero, the
+// kHistBig pass recomputes the transforms and adds the large values to the
+// global histogram one by one.
+constexpr int kHistBins = 2048;
 
 // One S-box evaluation as the kernels see it.
 struct JobDesc {
@@ -80,6 +87,8 @@ struct KParams {
   int nblk_log;          // n - 16
   long long row0;        // b-major store mode: row b goes to spec + (b - row0) * 2^n
   long long rows;        // ... and only rows [0, rows) exist there (0: all 2^m)
+  unsigned long long* hist;  // histogram modes: [2^(n-1) + 1] counts of |W|/2
+  unsigned long long* hist_over;  // values with |W|/2 >= kHistBins - 1 seen by kHist
 };
 
 typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));
@@ -187,7 +196,7 @@ constexpr int kLdsStride = kWG + 1;  // padded LDS row (odd number of words)
 // kernel with the two-round exchange fits two (<= 256 VGPRs per lane).
 template <int N, int P_, int MODE>
 constexpr int min_blocks() {
-  return (N == 16 && P_ == 8 && (MODE == kMax || MODE == kStoreB)) ? 2 : 1;
+  return (N == 16 && P_ == 8 && (MODE == kMax || MODE == kStoreB || MODE == kHist)) ? 2 : 1;  // kHistBig: 1
 }
 
 template <int N, int P_, int MODE>
@@ -203,13 +212,30 @@ __global__ __launch_bounds__(kWG, (min_blocks<N, P_, MODE>())) void k_walsh(cons
   constexpr int SWZ_SHIFT = (Q >= 1 && Q <= P - 1) ? (P - 1 - Q) : 0;
   constexpr int U2 = (Q >= 1 && Q <= P - 1) ? (1 << (P - 1 - Q)) : 1;
 
-  constexpr bool TWO_ROUND = ((MODE == kMax || MODE == kStoreB) && Q == P && P == 8);
+  constexpr bool TWO_ROUND =
+      ((MODE == kMax || MODE == kStoreB || MODE == kHist || MODE == kHistBig) && Q == P && P == 8);
   constexpr int LDS_WORDS = (Q == 0) ? 1 : (Q <= P - 1) ? NR * kWG : (TWO_ROUND ? 64 : NR) * kLdsStride;
   __shared__ uint32_t lds[LDS_WORDS];
   __shared__ int red[kWG / 64];
   __shared__ long long s_item;
+  __shared__ uint32_t hl[MODE == kHist ? kHistBins : 1];
 
   const int tid = threadIdx.x;
+  // histogram mode: counts since the last flush of hl (workgroup-uniform)
+  long long hcount = 0;
+  auto hist_flush = [&]() {
+    for (int k = tid; k < kHistBins; k += kWG) {
+      const uint32_t c = hl[k];
+      if (c) {
+        atomicAdd(k == kHistBins - 1 ? kp.hist_over : kp.hist + k, (unsigned long long)c);
+        hl[k] = 0;
+      }
+    }
+  };
+  if constexpr (MODE == kHist)
+    for (int k = tid; k < kHistBins; k += kWG) hl[k] = 0;  // ordered by the loop's first barrier
+  if constexpr (MODE == kHistBig)
+    if (*kp.hist_over == 0) return;  // no large value: nothing to add
   // thread group in this workgroup (wave-uniform when a group spans whole waves)
   const int g = (Q >= 6) ? __builtin_amdgcn_readfirstlane(tid >> Q) : (tid >> Q);
   const int tg = tid & ((1 << Q) - 1);    // thread within the group
@@ -288,6 +314,11 @@ __global__ __launch_bounds__(kWG, (min_blocks<N, P_, MODE>())) void k_walsh(cons
         gdst = (gint32*)(kp.blockout + ((size_t)slot << (16 + kp.nblk_log)) + ((size_t)xblk << 16));
       auto emit = [&](uint32_t a, int v) {  // v = -W(a,b)/2 (or the block value)
         mx = max(mx, v < 0 ? -v : v);
+        if constexpr (MODE == kHist) atomicAdd(&hl[min(v < 0 ? -v : v, kHistBins - 1)], 1u);
+        if constexpr (MODE == kHistBig) {
+          const int av = v < 0 ? -v : v;
+          if (av >= kHistBins - 1) atomicAdd(kp.hist + av, 1ull);
+        }
         // a < 2^16 here, so a 32-bit byte offset from a scalar row base suffices
         if constexpr (MODE == kStoreB)
           *(gint32*)((__attribute__((address_space(1))) char*)gdst + (uint32_t)(a << 2)) = jd.wscale * v;
@@ -505,16 +536,29 @@ __global__ __launch_bounds__(kWG, (min_blocks<N, P_, MODE>())) void k_walsh(cons
         for (int w = 0; w < WPG; ++w) gm = max(gm, red[g * WPG + w]);
         mx = gm;
       }
-      if constexpr (MODE != kBlock) {
+      if constexpr (MODE != kBlock && MODE != kHistBig) {
         if (tg == 0 && valid) {
           if (jd.maxabs) jd.maxabs[b] = 2 * mx;
           runmin = min(runmin, (1 << (n - 1)) - mx);
         }
       }
     }
-    if constexpr (MODE != kBlock) {
+    if constexpr (MODE != kBlock && MODE != kHistBig) {
       if (tg == 0 && runmin != 0x7fffffff) atomicMin(jd.nl, runmin);
     }
+    if constexpr (MODE == kHist) {
+      // keep every LDS count below 2^32
+      hcount += ((long long)GPW * C) << N;
+      if (hcount > (1LL << 31)) {
+        __syncthreads();
+        hist_flush();
+        hcount = 0;
+      }
+    }
+  }
+  if constexpr (MODE == kHist) {
+    __syncthreads();
+    hist_flush();
   }
 }
 
@@ -1266,6 +1310,105 @@ __global__ __launch_bounds__(256) void k_finalize_batch(const int* slotmax, long
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) cand = min(cand, __shfl_xor(cand, o, 64));
   if ((threadIdx.x & 63) == 0 && cand != 0x7fffffff) atomicMin(nl, cand);
+}
+
+// ---------------------------------------------------------------------------
+// Avalanche and bit independence: the autocorrelation of every component at
+// the unit input differences e_i,
+//   r_b(e_i) = sum_x (-1)^(b . (S(x) ^ S(x ^ e_i))) = sum_y c_i[y] (-1)^(b . y),
+// i.e. the 2^m-point transform over the output masks of the counts
+// c_i[y] = #{x : S(x) ^ S(x ^ e_i) = y}.
+// ---------------------------------------------------------------------------
+
+// c_i[y] += 2 for each pair {x, x ^ e_i}: one thread per (i, x with bit i clear).
+template <int EB>
+__global__ __launch_bounds__(256) void k_deriv_count(const void* S, int n, int m, int32_t* cnt) {
+  const long long half = 1LL << (n - 1);
+  const long long total = (long long)n * half;
+  const uint32_t mmask = (m >= 32) ? 0xffffffffu : ((1u << m) - 1u);
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total;
+       t += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(t >> (n - 1));
+    const long long j = t & (half - 1);
+    const long long x = ((j >> i) << (i + 1)) | (j & ((1LL << i) - 1));
+    const uint32_t y = (load_entry<EB>(S, x) ^ load_entry<EB>(S, x | (1LL << i))) & mmask;
+    atomicAdd(cnt + ((size_t)i << m) + y, 2);
+  }
+}
+
+// One pass of an in-place int32 Walsh-Hadamard transform of length 2^mlog
+// on each of the vectors: bits [lo, lo + R) through an LDS tile of 2^R rows
+// (stride 2^lo) by 2^cwlog consecutive columns, 2^(R + cwlog) <= 4096.
+// Every partial sum of a transform of counts is bounded by their total, so
+// int32 holds it.
+__global__ __launch_bounds__(256) void k_fwht_pass(int32_t* data, int mlog, int lo, int R, int cwlog) {
+  __shared__ int32_t t[4096];
+  const int tid = threadIdx.x;
+  const int CW = 1 << cwlog, TILE = 1 << (R + cwlog);
+  long long blk = blockIdx.x;
+  const long long ncolb = 1LL << (lo - cwlog);
+  const long long colb = blk % ncolb;
+  blk /= ncolb;
+  const long long nhi = 1LL << (mlog - lo - R);
+  const long long hi = blk % nhi;
+  const long long vec = blk / nhi;
+  int32_t* base = data + (vec << mlog) + (hi << (lo + R)) + (colb << cwlog);
+  for (int e = tid; e < TILE; e += 256) t[e] = base[((long long)(e >> cwlog) << lo) | (e & (CW - 1))];
+  __syncthreads();
+  for (int sb = 0; sb < R; ++sb) {
+    for (int e = tid; e < TILE / 2; e += 256) {
+      const int col = e & (CW - 1);
+      const int rr = e >> cwlog;
+      const int r0 = ((rr >> sb) << (sb + 1)) | (rr & ((1 << sb) - 1));
+      const int i0 = (r0 << cwlog) | col, i1 = ((r0 | (1 << sb)) << cwlog) | col;
+      const int32_t u = t[i0], v = t[i1];
+      t[i0] = u + v;
+      t[i1] = u - v;
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < TILE; e += 256) base[((long long)(e >> cwlog) << lo) | (e & (CW - 1))] = t[e];
+}
+
+// summary[0] = max_{i,j} |r_{e_j}(e_i)|, [1] = max_{i, j<k} |r_{e_j^e_k}(e_i)|
+// (-1 if m < 2), [2] = min_{j<k} (2^n - maxabs[e_j ^ e_k]) / 2 (-1 without
+// maxabs or if m < 2).  One workgroup.
+__global__ __launch_bounds__(256) void k_avalanche_summary(const int32_t* r, int n, int m, const int32_t* maxabs,
+                                                           int32_t* summary) {
+  __shared__ int s_val[3];
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    s_val[0] = 0;
+    s_val[1] = m >= 2 ? 0 : -1;
+    s_val[2] = (m >= 2 && maxabs) ? (1 << (n - 1)) : -1;
+  }
+  __syncthreads();
+  const int npair = m * (m + 1) / 2;  // (j, j) for the unit masks, (j, k > j) for pairs
+  int sac = 0, bic = 0, bnl = 0x7fffffff;
+  for (int t = tid; t < n * npair; t += 256) {
+    const int i = t / npair;
+    int q = t % npair, j = 0;
+    while (q >= m - j) {
+      q -= m - j;
+      ++j;
+    }
+    const int k = j + q;
+    const uint32_t b = (1u << j) | (1u << k);
+    const int v = r[((size_t)i << m) + b];
+    const int av = v < 0 ? -v : v;
+    if (k == j) sac = max(sac, av);
+    else {
+      bic = max(bic, av);
+      if (maxabs && i == 0) bnl = min(bnl, ((1 << n) - maxabs[b]) >> 1);
+    }
+  }
+  atomicMax(&s_val[0], sac);
+  if (m >= 2) {
+    atomicMax(&s_val[1], bic);
+    if (maxabs) atomicMin(&s_val[2], bnl);
+  }
+  __syncthreads();
+  if (tid < 3) summary[tid] = s_val[tid];
 }
 
 }  // namespace sbw

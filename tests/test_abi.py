@@ -119,3 +119,53 @@ def test_gray_code_block_mapping():
         i = inverse_gray(j)
         assert gray(i) == j
         assert sorted(gray(k) for k in range(i * R, (i + 1) * R)) == list(range(j * R, (j + 1) * R))
+
+
+@pytest.mark.parametrize("args,status", [
+    (dict(n=17), B.SBOX_ERR_UNSUPPORTED),
+    (dict(m=25), B.SBOX_ERR_UNSUPPORTED),
+    (dict(S=0), B.SBOX_ERR_INVALID_ARG),
+    (dict(hist=0), B.SBOX_ERR_INVALID_ARG),
+    (dict(eb=3), B.SBOX_ERR_INVALID_ARG),
+    (dict(ws=0), B.SBOX_ERR_WORKSPACE),
+    (dict(ws_bytes=64), B.SBOX_ERR_WORKSPACE),
+    (dict(ws=4096 + 8), B.SBOX_ERR_INVALID_ARG),
+])
+def test_histogram_rejects_invalid_arguments(lib, args, status):
+    a = dict(S=4096, n=8, m=8, eb=1, hist=8192, ws=4096, ws_bytes=1 << 20)
+    a.update(args)
+    assert B.sbox_walsh_histogram(a["S"], a["n"], a["m"], a["eb"], a["hist"], 0, 0, a["ws"], a["ws_bytes"],
+                                  0) == status
+    assert B.sbox_last_error() != ""
+
+
+def test_histogram_workspace_query(lib):
+    assert B.sbox_walsh_histogram_workspace_bytes(16, 16) > B.sbox_walsh_nl_workspace_bytes(16, 16, 0)
+    assert B.sbox_walsh_histogram_workspace_bytes(17, 4) == 0
+    assert B.sbox_walsh_histogram_workspace_bytes(8, 25) == 0
+
+
+@pytest.mark.parametrize("args,status", [
+    (dict(n=25), B.SBOX_ERR_UNSUPPORTED),
+    (dict(m=21), B.SBOX_ERR_UNSUPPORTED),
+    (dict(n=22, m=19), B.SBOX_ERR_UNSUPPORTED),
+    (dict(S=0), B.SBOX_ERR_INVALID_ARG),
+    (dict(summary=0), B.SBOX_ERR_INVALID_ARG),
+    (dict(eb=5), B.SBOX_ERR_INVALID_ARG),
+    (dict(ws=0), B.SBOX_ERR_WORKSPACE),
+    (dict(ws_bytes=1024), B.SBOX_ERR_WORKSPACE),
+    (dict(ws=4096 + 4), B.SBOX_ERR_INVALID_ARG),
+])
+def test_avalanche_rejects_invalid_arguments(lib, args, status):
+    a = dict(S=4096, n=8, m=8, eb=1, r=0, summary=8192, ws=4096, ws_bytes=1 << 20)
+    a.update(args)
+    assert B.sbox_avalanche(a["S"], a["n"], a["m"], a["eb"], a["r"], a["summary"], 0, a["ws"], a["ws_bytes"],
+                            0) == status
+    assert B.sbox_last_error() != ""
+
+
+def test_avalanche_workspace_query(lib):
+    assert B.sbox_avalanche_workspace_bytes(16, 16) == 16 * 65536 * 4
+    assert B.sbox_avalanche_workspace_bytes(24, 16) == 24 * 65536 * 4
+    assert B.sbox_avalanche_workspace_bytes(8, 21) == 0
+    assert B.sbox_avalanche_workspace_bytes(0, 4) == 0

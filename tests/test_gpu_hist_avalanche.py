@@ -1,0 +1,152 @@
+"""GPU parity of the |W| histogram and of the unit-difference
+autocorrelations (strict avalanche / bit independence) against the oracle,
+bit-exact, through the C ABI."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1912_03732_amd import binding as B
+from paper_1912_03732_amd import inputs
+from tests.gpu_util import dev_table, table
+from tests.test_oracle import apply_linear, random_invertible
+
+pytestmark = pytest.mark.gpu
+NT = 16
+
+
+def gpu_hist(S, n, m):
+    hist, nl, mx = B.walsh_histogram(dev_table(S, m), n, m, maxabs=True)
+    return hist.cpu().numpy().astype(np.uint64), nl, mx.cpu().numpy()
+
+
+def check_hist(S, n, m):
+    h, nl, mx = gpu_hist(S, n, m)
+    ref = oracle.walsh_histogram(S, n, m, nthreads=NT)
+    assert np.array_equal(h, ref), (n, m, np.nonzero(h != ref)[0][:8])
+    onl, omx = oracle.walsh_nl(S, n, m, nthreads=NT)
+    assert nl == onl and np.array_equal(mx, omx)
+    return h
+
+
+# ------------------------------------------------------------- histogram ---
+
+@pytest.mark.parametrize("n", list(range(1, 17)))
+def test_histogram_every_n(n):
+    m = {1: 3, 2: 2, 3: 5, 16: 3}.get(n, min(n, 9))
+    check_hist(table(n, m, 20000 + n), n, m)
+
+
+@pytest.mark.parametrize("n,m", [(8, 8), (12, 12), (13, 4), (14, 6), (15, 2)])
+def test_histogram_shapes(n, m):
+    check_hist(table(n, m, 20100 + n + m, kind="perm"), n, m)
+
+
+@pytest.mark.parametrize("n", [5, 12, 13, 16])
+def test_histogram_affine_box_uses_the_large_value_pass(n):
+    """Affine components put |W| = 2^n (bin 2^(n-1)) in every column: past the
+    LDS bins from n = 12 on, so the second pass must add them."""
+    A = random_invertible(n, inputs.rng(20200 + n))
+    m = min(n, 6)
+    S = (apply_linear(A, np.arange(1 << n)) ^ 3) & ((1 << m) - 1)
+    h = check_hist(S, n, m)
+    assert h[1 << (n - 1)] == (1 << m) - 1
+
+
+def test_histogram_constant_component_16():
+    """n = 16 with a constant output bit: |W| = 2^16 at a = 0 for that mask
+    (the int16 wrap case of the transform)."""
+    S = (inputs.permutation(16, inputs.rng(20300)).astype(np.uint32) & 0x7) | 0x8
+    check_hist(S, 16, 4)
+
+
+def test_histogram_aes():
+    h = check_hist(inputs.aes_sbox(), 8, 8)
+    assert int(np.nonzero(h)[0].max()) == 16  # max |W| = 32, NL = 112
+
+
+def test_histogram_16x16_full():
+    """The 16 x 16 permutation: all 2^32 coefficients, against the oracle."""
+    S = inputs.workload_16x16()["perm"]
+    h = check_hist(S, 16, 16)
+    k = np.arange(h.size, dtype=np.int64)
+    assert int(h.astype(np.int64).sum()) == 65536 * 65535
+    assert int((h.astype(np.int64) * (2 * k) ** 2).sum()) == 65535 * (1 << 32)
+
+
+# ------------------------------------------------------------- avalanche ---
+
+def check_avalanche(S, n, m, full=True):
+    Sd = dev_table(S, m)
+    _, mx, _ = B.walsh_nl(Sd, n, m)
+    summ, r = B.avalanche(Sd, n, m, maxabs=mx)
+    osumm, orr = oracle.avalanche(S, n, m, full=full, nthreads=NT)
+    assert summ == osumm, (summ, osumm)
+    r = r.cpu().numpy()
+    if full:
+        assert np.array_equal(r, orr)
+    return summ, r
+
+
+@pytest.mark.parametrize("n,m", [(1, 1), (1, 4), (3, 2), (5, 5), (8, 8), (9, 3), (12, 12), (6, 14), (13, 11)])
+def test_avalanche_shapes(n, m):
+    check_avalanche(table(n, m, 20400 + n + m, kind="perm"), n, m)
+
+
+def test_avalanche_aes():
+    summ, _ = check_avalanche(inputs.aes_sbox(), 8, 8)
+    assert summ["bic_nl"] == 112
+
+
+@pytest.mark.parametrize("n", [7, 10])
+def test_avalanche_linear_box(n):
+    A = random_invertible(n, inputs.rng(20500 + n))
+    summ, _ = check_avalanche(apply_linear(A, np.arange(1 << n)), n, n)
+    assert summ["sac_max"] == 1 << n and summ["bic_nl"] == 0
+
+
+def test_avalanche_16x16_sampled():
+    """16 x 16 permutation: the summary against the oracle (which sums the
+    unit and pair masks from the definition) and r on a sample of masks."""
+    S = inputs.workload_16x16()["perm"]
+    summ, r = check_avalanche(S, 16, 16, full=False)
+    masks = np.concatenate([[0, 1, 2, 3, 0x8001, 0xFFFF], inputs.rng(20600).integers(0, 1 << 16, 64)])
+    ref = oracle.unit_autocorrelation_masks(S, 16, 16, masks, nthreads=NT)
+    assert np.array_equal(r[:, masks], ref)
+
+
+@pytest.mark.parametrize("n,m", [(20, 4), (17, 18)])
+def test_avalanche_large_properties(n, m):
+    """Beyond the oracle's range: r_0(e_i) = 2^n; sum_b r_b(e_i) = 2^m
+    #{x : D_i(x) = 0}; sum_b r_b(e_i)^2 = 2^m sum_y c_i[y]^2, with the counts
+    c_i of the derivative values taken by numpy; r on sampled masks against
+    the oracle's definition."""
+    S = table(n, m, 20700 + n)
+    Sd = dev_table(S, m)
+    summ, r = B.avalanche(Sd, n, m)
+    r = r.cpu().numpy().astype(np.int64)
+    x = np.arange(1 << n)
+    for i in range(n):
+        d = (S[x] ^ S[x ^ (1 << i)]).astype(np.int64)
+        c = np.bincount(d, minlength=1 << m).astype(np.int64)
+        assert r[i, 0] == 1 << n
+        assert r[i].sum() == (1 << m) * c[0]
+        assert (r[i] ** 2).sum() == (1 << m) * (c ** 2).sum()
+    masks = inputs.rng(20710).integers(0, 1 << m, 6)
+    ref = oracle.unit_autocorrelation_masks(S, n, m, masks, nthreads=NT)
+    assert np.array_equal(r[:, masks], ref)
+    assert summ["bic_nl"] == -1
+
+
+def test_avalanche_without_r_uses_workspace():
+    import torch
+    n, m = 10, 8
+    S = table(n, m, 20800)
+    Sd = dev_table(S, m)
+    summ = torch.empty(3, dtype=torch.int32, device="cuda")
+    ws = B.Workspace(B.sbox_avalanche_workspace_bytes(n, m))
+    st = int(torch.cuda.current_stream().cuda_stream)
+    assert B.sbox_avalanche(Sd.data_ptr(), n, m, Sd.element_size(), 0, summ.data_ptr(), 0, ws.ptr, ws.nbytes,
+                            st) == B.SBOX_OK
+    torch.cuda.synchronize()
+    osumm, _ = oracle.avalanche(S, n, m, full=False)
+    assert summ.cpu().tolist() == [osumm["sac_max"], osumm["bic_sac_max"], -1]

@@ -174,3 +174,11 @@ def test_avalanche_summary_consistent(n, m):
     assert summ["bic_sac_max"] == int(np.abs(r[:, pairs]).max())
     _, maxabs = oracle.walsh_nl(S, n, m)
     assert summ["bic_nl"] == min(((1 << n) - int(maxabs[b])) // 2 for b in pairs)
+
+
+def test_unit_autocorrelation_masks_match_full():
+    n, m = 7, 6
+    S = inputs.random_function(n, m, inputs.rng(1780))
+    _, r = oracle.avalanche(S, n, m)
+    masks = [0, 1, 5, 17, 63, 40]
+    assert np.array_equal(oracle.unit_autocorrelation_masks(S, n, m, masks), r[:, masks])
