@@ -281,6 +281,38 @@ def bench_extra(torch, B, inputs, dev):
         out["criteria_%dx%d" % (n, n)] = {"ms": ms, "coeff_per_s": coeffs / (ms * 1e-3),
                                           "int_ops_per_s": 2 * n * coeffs / (ms * 1e-3),
                                           "summary": summ.cpu().tolist()[:6]}
+    # |W| histogram over all nonzero masks (fused into the transform)
+    for name, S_host, n in (("8x8_perm", w8["perm"], 8), ("16x16_perm", inputs.workload_16x16()["perm"], 16)):
+        S = B.table_to_device(S_host, n, device=dev)
+        hist = torch.empty((1 << (n - 1)) + 1, dtype=torch.int64, device=dev)
+        nl = torch.empty(1, dtype=torch.int32, device=dev)
+        ws = B.Workspace(B.sbox_walsh_histogram_workspace_bytes(n, n), dev)
+        sptr = int(torch.cuda.current_stream(dev).cuda_stream)
+
+        def hcall():
+            st = B.sbox_walsh_histogram(S.data_ptr(), n, n, S.element_size(), hist.data_ptr(), 0, nl.data_ptr(),
+                                        ws.ptr, ws.nbytes, sptr)
+            if st != 0:
+                raise RuntimeError(B.last_error())
+        ms = _time_call(torch, hcall, 3 if n == 16 else 20)
+        coeffs = (1 << n) * ((1 << n) - 1)
+        h = hist.cpu()
+        out["histogram_%s" % name] = {"ms": ms, "coeff_per_s": coeffs / (ms * 1e-3), "nl": int(nl.item()),
+                                      "max_bin": int(torch.nonzero(h).max())}
+    # unit-difference autocorrelations (strict avalanche / bit independence)
+    for name, S_host, n in (("8x8_perm", w8["perm"], 8), ("16x16_perm", inputs.workload_16x16()["perm"], 16)):
+        S = B.table_to_device(S_host, n, device=dev)
+        r = torch.empty(n << n, dtype=torch.int32, device=dev)
+        summ = torch.empty(3, dtype=torch.int32, device=dev)
+        sptr = int(torch.cuda.current_stream(dev).cuda_stream)
+
+        def acall():
+            st = B.sbox_avalanche(S.data_ptr(), n, n, S.element_size(), r.data_ptr(), summ.data_ptr(), 0, 0, 0,
+                                  sptr)
+            if st != 0:
+                raise RuntimeError(B.last_error())
+        ms = _time_call(torch, acall, 20)
+        out["avalanche_%s" % name] = {"ms": ms, "summary": summ.cpu().tolist()}
     return out
 
 
