@@ -258,6 +258,7 @@ def bench_extra(torch, B, inputs, dev):
     out["8x8_perm_fused"] = single(w8["perm"], 8, 8, reps=50)
     out["8x8_perm_spectrum_b"] = single(w8["perm"], 8, 8, 1, reps=50)
     out["8x8_perm_spectrum_a"] = single(w8["perm"], 8, 8, 2, reps=50)
+    out["12x12_perm_fused"] = single(inputs.permutation(12, inputs.rng(inputs.SEED_BASE + 6)), 12, 12, reps=50)
     ns = inputs.workload_nonsquare()
     out["16x20_fused"] = single(ns["s16x20"], 16, 20, reps=2)
     out["20x16_fused"] = single(ns["s20x16"], 20, 16, reps=1)

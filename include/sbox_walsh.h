@@ -77,11 +77,12 @@ typedef enum {
  *   chunk   : consecutive masks (in Gray-code order) one thread group
  *             walks per work item.
  *   grid    : number of persistent workgroups (0: fill every CU).
- *   variant : butterfly engine for the n = 16 fused maximum (no spectrum):
- *             0 the library's choice (currently 2), 1 packed 16-bit VALU
- *             butterflies, 2 matrix cores (fp16 MFMA Hadamard blocks, exact);
- *             other sizes and modes accept 0 or 1 only.  Batched launches
- *             and plans apply it to their n = 16 boxes.
+ *   variant : butterfly engine for the n = 12 and n = 16 fused maximum (no
+ *             spectrum): 0 the library's choice (currently 2), 1 packed
+ *             16-bit VALU butterflies, 2 matrix cores (fp16 MFMA Hadamard
+ *             blocks, exact; split_p does not apply); other sizes and modes
+ *             accept 0 or 1 only.  Batched launches and plans apply it to
+ *             their n = 12 and n = 16 boxes.
  */
 typedef struct sbox_tuning {
     int32_t split_p;

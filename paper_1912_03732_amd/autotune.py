@@ -44,10 +44,11 @@ def candidates(n: int, m: int, cus: int = 256) -> List[Tuple[int, int, int]]:
     for p in valid_splits(n):
         for c in chunks:
             for g in grids:
-                out.append((p if n > 8 else 0, c, g, 1 if n == 16 else 0))
-    if n == 16:  # the matrix-core engine
+                out.append((p if n > 8 else 0, c, g, 1 if n in (12, 16) else 0))
+    if n in (12, 16):  # the matrix-core engine
         for c in chunks:
-            out.append((0, c, 0, 2))
+            for g in grids:
+                out.append((0, c, g, 2))
     return out
 
 

@@ -204,18 +204,24 @@ long long inverse_gray(long long j) {
   return r;
 }
 
-// Butterfly engine of the n = 16 fused maximum: the library default is the
-// matrix-core kernel (variant 2); variant 1 selects the packed 16-bit VALU one.
-constexpr int kDefaultVariant16 = 2;
-// LDS exchange rounds of the matrix-core kernel (2: 64 KiB, 4: 32 KiB per workgroup)
+// Butterfly engine of the n = 12 and n = 16 fused maximum: the library
+// default is the matrix-core kernel (variant 2); variant 1 selects the packed
+// 16-bit VALU one.
+constexpr int kDefaultVariant = 2;
+// LDS exchange rounds of the n = 16 matrix-core kernel (2: 64 KiB, 4: 32 KiB per workgroup)
 #ifndef SBW_MFMA_ROUNDS
 #define SBW_MFMA_ROUNDS 4
 #endif
 constexpr int kMfmaRounds = SBW_MFMA_ROUNDS;
-bool use_mfma16(const sbox_tuning* tun) {
-  const int v = (tun && tun->variant) ? tun->variant : kDefaultVariant16;
+bool mfma_n(int n) { return n == 12 || n == 16; }
+bool use_mfma(int n, const sbox_tuning* tun) {
+  if (!mfma_n(n)) return false;
+  const int v = (tun && tun->variant) ? tun->variant : kDefaultVariant;
   return v == 2;
 }
+KFn mfma_kernel(int n) { return n == 16 ? &k_walsh_mfma16<kMfmaRounds> : &k_walsh_mfma12; }
+// masks a workgroup works on at once (thread groups per item slot)
+int mfma_groups(int n) { return n == 16 ? 1 : kWG / 64; }
 
 int mode_of(int layout) { return layout == 1 ? kStoreB : (layout == 2 ? kStoreA : kMax); }
 
@@ -232,7 +238,15 @@ void pick_chunk(long long masks_total, int groups, int grid_cap, int chunk_req, 
     *chunk = chunk_req;
     return;
   }
+  // about 8 items per workgroup; but a new item rebuilds its first mask
+  // from up to m slices while each further mask costs one, so small problems
+  // still take up to 4 masks per item as long as every CU gets an item
   long long c = masks_total / ((long long)groups * grid_cap * 8);
+  if (c < 4) {
+    int cus = 0;
+    if (device_info(&cus) != SBOX_OK || cus < 1) cus = 1;
+    c = std::max(c, std::min(4LL, masks_total / ((long long)groups * cus)));
+  }
   c = std::max(1LL, std::min(64LL, c));
   *chunk = (int)c;
 }
@@ -397,21 +411,23 @@ sbox_status run_single(const void* S, int n, int m, int eb, int32_t* maxabs, int
     return SBOX_OK;
   }
 
-  if (n == 16 && layout == 0 && !hist && use_mfma16(tun)) {
-    const void* fn = (const void*)&k_walsh_mfma16<kMfmaRounds>;
+  if (layout == 0 && !hist && use_mfma(n, tun)) {
+    const void* fn = (const void*)mfma_kernel(n);
     int occ = 1;
     s = occupancy(fn, &occ);
     if (s) return s;
     const long long M = 1LL << m;
     const int grid_cap = (tun && tun->grid) ? tun->grid : occ * cus;
+    const int groups = mfma_groups(n);
     int chunk = 1;
-    pick_chunk(M, 1, grid_cap, tun ? tun->chunk : 0, &chunk);
+    pick_chunk(M, groups, grid_cap, tun ? tun->chunk : 0, &chunk);
+    const long long per_item = (long long)groups * chunk;
     KParams kp{};
     kp.job0 = jd;
     kp.njobs = 1;
     kp.chunk = chunk;
     kp.queue = queue;
-    kp.total_items = (M + chunk - 1) / chunk;
+    kp.total_items = (M + per_item - 1) / per_item;
     const int grid = (int)std::min<long long>(grid_cap, kp.total_items);
     void* args[] = {&kp};
     return launch(fn, dim3(grid), dim3(kWG), args, st);
@@ -599,14 +615,14 @@ sbox_status plan_batch(const sbox_job* jobs, int count, const sbox_tuning* tun, 
     c.layout = layout;
     const int p = (tun && tun->split_p && n > 8) ? tun->split_p : default_split(n);
     if (n > 8 && !split_valid(n, p)) return fail(SBOX_ERR_INVALID_ARG, "split_p=%d invalid for n=%d", p, n);
-    c.fn = (n == 16 && layout == 0 && use_mfma16(tun)) ? &k_walsh_mfma16<kMfmaRounds>
-                                                       : lookup_kernel(n, p, mode_of(base_layout(layout)));
+    const bool mc = layout == 0 && use_mfma(n, tun);
+    c.fn = mc ? mfma_kernel(n) : lookup_kernel(n, p, mode_of(base_layout(layout)));
     if (!c.fn) return fail(SBOX_ERR_INVALID_ARG, "no kernel for n=%d split_p=%d layout=%d", n, p, layout);
     int occ = 1;
     s = occupancy((const void*)c.fn, &occ);
     if (s) return s;
     const int Q = n <= 8 ? 0 : n - p;
-    const int groups = kWG >> Q;
+    const int groups = mc ? mfma_groups(n) : kWG >> Q;
     const int grid_cap = (tun && tun->grid) ? tun->grid : occ * cus;
     long long masks_total = 0;
     for (int k = i; k < jend; ++k) masks_total += 1LL << jobs[order[k]].m;
@@ -747,8 +763,8 @@ sbox_status sbox_walsh_nl_ex(const void* S, int n, int m, int s_elem_bytes, int3
       return fail(SBOX_ERR_INVALID_ARG, "negative tuning field");
     if (tuning->variant < 0 || tuning->variant > 2)
       return fail(SBOX_ERR_INVALID_ARG, "tuning variant %d (0, 1 or 2)", tuning->variant);
-    if (tuning->variant == 2 && !(n == 16 && layout == 0))
-      return fail(SBOX_ERR_INVALID_ARG, "the matrix-core variant covers n = 16 without a spectrum only");
+    if (tuning->variant == 2 && !(mfma_n(n) && layout == 0))
+      return fail(SBOX_ERR_INVALID_ARG, "the matrix-core variant covers n = 12 and 16 without a spectrum only");
     if (tuning->split_p && n > 8 && n <= 16 && !split_valid(n, tuning->split_p))
       return fail(SBOX_ERR_INVALID_ARG, "split_p=%d invalid for n=%d", tuning->split_p, n);
     if (tuning->split_p && n <= 16 && n > 8 && layout != 0 && tuning->split_p != default_split(n))

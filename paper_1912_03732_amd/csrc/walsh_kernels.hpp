@@ -798,6 +798,153 @@ __global__ __launch_bounds__(kWG, ROUNDS) void k_walsh_mfma16(const KParams kp) 
 }
 
 // ---------------------------------------------------------------------------
+// n = 12, max mode, matrix-core variant: one wave per mask, four masks per
+// workgroup, no workgroup barrier inside a mask.
+//
+// Lane l holds words 2l, 2l + 1 of the mask (x5 = which word, x6..x11 = l).
+//   1. Popcount stages as fp16 bit patterns (1536 + c', as in the n = 16
+//      kernel), the x5 pair packed into one register.
+//   2. A wave-private LDS transpose: lane (x8, x9, a'3, a'4, x10, x11)
+//      receives register (x6, x7, a'0, a'1, a'2) (the XOR swizzle of the
+//      address keeps both sides free of bank conflicts).
+//   3. Pass 1, for each (a'0, a'1, a'2): the registers over (x6, x7) with
+//      their x5 halves are the A operand of v_mfma_f32_16x16x32_f16 with rows
+//      (x8, x9, a'3, a'4) = lane bits 0..3 and K slots (x5, x6, x7, x10, x11),
+//      against the two halves of H_32; the accumulator input removes the
+//      offset from column 0.  |value| <= 512, cast to fp16 exactly.
+//   4. Pass 2: the four results of a lane are rows 4 (lane / 16) + i, i.e. K
+//      slots (x8, x9, a'3, a'4) of v_mfma_f32_16x16x16_f16 against
+//      H_4 (x8, x9) (x) I_4 (a'3, a'4), which transforms x8, x9 and passes the
+//      rest through.  |value| <= 2048, exact.
+// Every bit of x is transformed once (5 + 5 + 2).
+// ---------------------------------------------------------------------------
+typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(kWG, 4) void k_walsh_mfma12(const KParams kp) {
+  constexpr int NW = 2;
+  constexpr int GPW = kWG / 64;               // masks (waves) per workgroup
+  __shared__ uint32_t lds[GPW * 32 * 64];     // 8 KiB per wave
+  __shared__ long long s_item;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int C = kp.chunk;
+  uint32_t* wl = lds + wave * (32 * 64);
+
+  f16x8 hb0, hb1;
+  f16x4 hc;
+  {
+    const int g = lane >> 4, n = lane & 15;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int kappa = j + 8 * g;
+      hb0[j] = hsign(kappa & n);
+      hb1[j] = hsign(kappa & (n + 16));
+    }
+    // H_4 on K bits 0..1 and output bits 0..1, identity on bits 2..3
+#pragma unroll
+    for (int j = 0; j < 4; ++j) hc[j] = (g == (n >> 2)) ? hsign(j & n & 3) : (_Float16)0.0f;
+  }
+  const float fix = (lane & 15) == 0 ? -49152.0f : 0.0f;
+  const f32x4 cfix = {fix, fix, fix, fix};
+  const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+  // exchange addresses: source a' -> (register, lane) of the receiver
+  const int xs = lane & 3;                                  // x6, x7
+  const int dl0 = ((lane >> 2) & 3) | (((lane >> 4) & 3) << 4);  // x8, x9, x10, x11
+
+  for (;;) {
+    if (tid == 0) s_item = (long long)atomicAdd(kp.queue, 1);
+    __syncthreads();
+    const long long item = __builtin_amdgcn_readfirstlane((int)s_item);
+    __syncthreads();
+    if (item >= kp.total_items) break;
+    JobDesc jd;
+    long long li;
+    if (kp.jobs == nullptr) {
+      jd = kp.job0;
+      li = item;
+    } else {
+      int lo = 0, hi = kp.njobs - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (kp.jobs[mid].item_begin <= item) lo = mid; else hi = mid - 1;
+      }
+      jd = kp.jobs[lo];
+      li = item - jd.item_begin;
+    }
+    const long long kfirst = (li * GPW + wave) * (long long)C;
+    const long long kend = 1LL << jd.m;
+    const long long wb = (long long)lane * NW;
+    const int n = jd.n;
+    int runmin = 0x7fffffff;
+    uint32_t G[NW], Fn[NW];
+
+    for (int step = 0; step < C; ++step) {
+      const long long k = kfirst + step;
+      if (k >= kend) break;  // wave-uniform
+      if (step == 0) {
+        G[0] = G[1] = 0;
+        const long long gk = gray(k);
+        for (int i = 0; i < jd.m; ++i)
+          if ((gk >> i) & 1) load_words<NW>(G, jd.F + (long long)i * jd.nwords + wb, true);
+      } else {
+        G[0] ^= Fn[0];
+        G[1] ^= Fn[1];
+      }
+      if (step + 1 < C && k + 1 < kend) {
+        const int i = __builtin_ctzll((unsigned long long)(k + 1));
+        load_words<NW>(Fn, jd.F + (long long)i * jd.nwords + wb, false);
+      }
+      // ---- 1-2. popcounts into the wave's LDS tile
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int a = 0; a < 32; ++a) {
+        const uint32_t c0 = __builtin_popcount(G[0] ^ walsh_mask(a)) + (0x6600 - 16);
+        const uint32_t c1 = __builtin_popcount(G[1] ^ walsh_mask(a)) + (0x6600 - 16);
+        const int dreg = xs + 4 * (a & 7);
+        const int dlane = dl0 | ((a >> 3) << 2);
+        wl[dreg * 64 + (dlane ^ (xs << 2))] = __builtin_amdgcn_perm(c1, c0, 0x05040100u);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      uint32_t R[32];
+#pragma unroll
+      for (int d = 0; d < 32; ++d) R[d] = wl[d * 64 + (lane ^ ((d & 3) << 2))];
+      // ---- 3-4. the two passes and the maximum
+      float m0 = 0.0f, m1 = 0.0f;
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const f16x8 av = as_f16x8(R[4 * t], R[4 * t + 1], R[4 * t + 2], R[4 * t + 3]);
+        const f32x4 d0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(av, hb0, cfix, 0, 0, 0);
+        const f32x4 d1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(av, hb1, zero, 0, 0, 0);
+        f16x4 a0, a1;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          a0[i] = (_Float16)d0[i];
+          a1[i] = (_Float16)d1[i];
+        }
+        const f32x4 e0 = __builtin_amdgcn_mfma_f32_16x16x16f16(a0, hc, zero, 0, 0, 0);
+        const f32x4 e1 = __builtin_amdgcn_mfma_f32_16x16x16f16(a1, hc, zero, 0, 0, 0);
+        m0 = fmaxf(fmaxf(m0, fabsf(e0[0])), fabsf(e1[0]));
+        m1 = fmaxf(fmaxf(m1, fabsf(e0[1])), fabsf(e1[1]));
+        m0 = fmaxf(fmaxf(m0, fabsf(e0[2])), fabsf(e1[2]));
+        m1 = fmaxf(fmaxf(m1, fabsf(e0[3])), fabsf(e1[3]));
+      }
+      int mx = (int)fmaxf(m0, m1);
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) mx = max(mx, __shfl_xor(mx, o, 64));
+      if (lane == 0 && k != 0) {
+        if (jd.maxabs) jd.maxabs[(uint32_t)gray(k)] = 2 * mx;
+        runmin = min(runmin, (1 << (n - 1)) - mx);
+      }
+    }
+    if (lane == 0 && runmin != 0x7fffffff) atomicMin(jd.nl, runmin);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // n = 16 + L, 1 <= L <= 4, max mode: recompute instead of materialising.
 //
 // Write x = (x_hi : L bits, x_lo : 16 bits).  For a fixed high output index

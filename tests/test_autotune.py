@@ -20,8 +20,10 @@ def test_valid_splits_match_the_compiled_kernels():
 
 def test_candidates_cover_chunks_and_grids():
     c = autotune.candidates(12, 12, cus=256)
-    assert (6, 1, 0, 0) in c and (8, 64, 512, 0) in c
-    assert all(p in (6, 7, 8) for p, _, _, _ in c)
+    assert (6, 1, 0, 1) in c and (8, 64, 512, 1) in c and (0, 8, 256, 2) in c
+    assert all(p in (6, 7, 8) for p, _, _, v in c if v == 1)
+    c10 = autotune.candidates(10, 10, cus=256)
+    assert (6, 1, 0, 0) in c10 and {v for _, _, _, v in c10} == {0}
     c16 = autotune.candidates(16, 16)
     assert {p for p, _, _, v in c16 if v == 1} == {8} and {g for _, _, g, _ in c16} == {0}
     assert {v for _, _, _, v in c16} == {1, 2}

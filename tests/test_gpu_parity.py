@@ -305,6 +305,37 @@ def test_valu_variant_16(m, kind):
     check_against_oracle(S, 16, m, nthreads=NT, tuning=B.sbox_tuning(0, 0, 0, 1))
 
 
+@pytest.mark.parametrize("m,kind", [(1, "random"), (5, "random"), (12, "perm"), (12, "inv"), (12, "const"),
+                                    (12, "affine"), (17, "random")])
+def test_matrix_core_variant_12(m, kind):
+    """n = 12 fused maximum on the matrix cores (one wave per mask), bit-exact."""
+    if kind == "perm":
+        S = inputs.permutation(12, inputs.rng(6101))
+    elif kind == "inv":
+        S = inputs.gf_inversion(12)
+    elif kind == "const":
+        S = (inputs.permutation(12, inputs.rng(6102)) & 0x7FF).astype(np.uint16)
+    elif kind == "affine":
+        S = (np.arange(1 << 12) * 5 ^ 0x123) & 0xFFF
+    else:
+        S = table(12, m, 16000 + m)
+    nl, mx = check_against_oracle(S, 12, m, nthreads=NT, tuning=B.sbox_tuning(0, 0, 0, 2))
+    if kind == "inv":
+        assert nl == (1 << 11) - (1 << 6)
+    if kind in ("const", "affine"):
+        assert nl == 0
+
+
+@pytest.mark.parametrize("chunk,grid", [(1, 1), (3, 7), (64, 0)])
+def test_matrix_core_12_launch_shapes(chunk, grid):
+    S = table(12, 10, 16100 + chunk)
+    check_against_oracle(S, 12, 10, nthreads=NT, tuning=B.sbox_tuning(0, chunk, grid, 2))
+
+
+def test_valu_variant_12():
+    check_against_oracle(table(12, 12, 16200), 12, 12, nthreads=NT, tuning=B.sbox_tuning(0, 0, 0, 1))
+
+
 @pytest.mark.parametrize("chunk,grid", [(1, 1), (7, 33), (64, 0)])
 def test_matrix_core_variant_launch_shapes(chunk, grid):
     S = table(16, 9, 15100 + chunk)
