@@ -340,3 +340,26 @@ def test_valu_variant_12():
 def test_matrix_core_variant_launch_shapes(chunk, grid):
     S = table(16, 9, 15100 + chunk)
     check_against_oracle(S, 16, 9, nthreads=NT, tuning=B.sbox_tuning(0, chunk, grid, 2))
+
+
+@pytest.mark.parametrize("n,m", [(12, 9), (16, 6)])
+def test_matrix_core_without_maxabs(n, m):
+    """NL alone (maxabs_per_b NULL) on the matrix-core engines."""
+    S = table(n, m, 16300 + n)
+    nl, mx, _ = B.walsh_nl(dev_table(S, m), n, m, maxabs=False)
+    assert mx is None and nl == oracle.walsh_nl(S, n, m, nthreads=NT)[0]
+
+
+@pytest.mark.parametrize("n,m", [(12, 20), (16, 18)])
+def test_matrix_core_many_masks_sampled(n, m):
+    """2^m masks well past one pass of the grid: sampled masks against the
+    oracle (which transforms each listed mask), NL against the sample's
+    bound and the per-mask identity maxabs >= 2^(n/2) (Parseval)."""
+    S = table(n, m, 16400 + n + m)
+    nl, mx, _ = B.walsh_nl(dev_table(S, m), n, m)
+    mx = mx.cpu().numpy()
+    g = inputs.rng(16410 + m)
+    masks = np.unique(np.concatenate([[1, 2, (1 << m) - 1, 1 << (m - 1)], g.integers(1, 1 << m, 300)]))
+    assert np.array_equal(mx[masks], oracle.maxabs_for_masks(S, n, m, masks, nthreads=NT))
+    assert mx[0] == 1 << n and np.all(mx[1:] >= 1 << (n // 2))
+    assert nl == (1 << (n - 1)) - int(mx[1:].max()) // 2
