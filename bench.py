@@ -31,6 +31,7 @@ PEAK_PK16_TOPS = 2 * PEAK_INT32_TOPS
 # rows, the work of 16 x 16 x 5 = 1,280 butterfly add/subs; 1,024 SIMDs at
 # 2.4 GHz give 1.966e14 butterfly ops/s, the fastest unit for this work.
 PEAK_MFMA_BUTTERFLY_TOPS = 256 * 4 * 2.4e9 / 16 * 1280 / 1e12
+PEAK_HBM_GBS = 8000.0
 
 
 def parse():
@@ -251,7 +252,15 @@ def bench_extra(torch, B, inputs, dev):
         row = {"ms": ms, "coeff_per_s": coeffs / (ms * 1e-3), "int_ops_per_s": n * coeffs / (ms * 1e-3),
                "nl": int(nl.item())}
         if layout:
-            row["spectrum_GB_per_s"] = 4 * (1 << (n + m)) / (ms * 1e-3) / 1e9
+            # a stored spectrum makes the call HBM-bound: 4 bytes per coefficient
+            gbs = 4 * (1 << (n + m)) / (ms * 1e-3) / 1e9
+            row["spectrum_GB_per_s"] = gbs
+            row["roofline"] = {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                               "frac": gbs / PEAK_HBM_GBS}
+        else:
+            peak = PEAK_MFMA_BUTTERFLY_TOPS if n in (12, 16) else PEAK_PK16_TOPS
+            tops = n * coeffs / (ms * 1e-3) / 1e12
+            row["roofline"] = {"bound": "alu", "achieved": tops, "peak": peak, "unit": "TOP/s", "frac": tops / peak}
         return row
 
     w8 = inputs.workload_8x8()
@@ -279,9 +288,13 @@ def bench_extra(torch, B, inputs, dev):
                 raise RuntimeError(B.last_error())
         ms = _time_call(torch, crit, 3 if n == 14 else 10)
         coeffs = (1 << n) * ((1 << n) - 1)
+        tops = 2 * n * coeffs / (ms * 1e-3) / 1e12
         out["criteria_%dx%d" % (n, n)] = {"ms": ms, "coeff_per_s": coeffs / (ms * 1e-3),
                                           "int_ops_per_s": 2 * n * coeffs / (ms * 1e-3),
-                                          "summary": summ.cpu().tolist()[:6]}
+                                          "summary": summ.cpu().tolist()[:6],
+                                          # two int32 transforms per mask through LDS
+                                          "roofline": {"bound": "alu", "achieved": tops, "peak": PEAK_INT32_TOPS,
+                                                       "unit": "TOP/s", "frac": tops / PEAK_INT32_TOPS}}
     # |W| histogram over all nonzero masks (fused into the transform)
     for name, S_host, n in (("8x8_perm", w8["perm"], 8), ("16x16_perm", inputs.workload_16x16()["perm"], 16)):
         S = B.table_to_device(S_host, n, device=dev)
@@ -298,8 +311,12 @@ def bench_extra(torch, B, inputs, dev):
         ms = _time_call(torch, hcall, 3 if n == 16 else 20)
         coeffs = (1 << n) * ((1 << n) - 1)
         h = hist.cpu()
+        tops = n * coeffs / (ms * 1e-3) / 1e12
         out["histogram_%s" % name] = {"ms": ms, "coeff_per_s": coeffs / (ms * 1e-3), "nl": int(nl.item()),
-                                      "max_bin": int(torch.nonzero(h).max())}
+                                      "max_bin": int(torch.nonzero(h).max()),
+                                      # the packed-int16 store-mode transform plus one LDS count per value
+                                      "roofline": {"bound": "alu", "achieved": tops, "peak": PEAK_PK16_TOPS,
+                                                   "unit": "TOP/s", "frac": tops / PEAK_PK16_TOPS}}
     # unit-difference autocorrelations (strict avalanche / bit independence)
     for name, S_host, n in (("8x8_perm", w8["perm"], 8), ("16x16_perm", inputs.workload_16x16()["perm"], 16)):
         S = B.table_to_device(S_host, n, device=dev)

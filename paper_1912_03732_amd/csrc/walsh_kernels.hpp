@@ -1346,7 +1346,8 @@ __global__ __launch_bounds__(256) void k_transpose_slab(const int32_t* slab, int
   for (int r = ty; r < 64; r += 4) {
     const long long a = a0 + r;
     const int j = j0 + tx;
-    if (j < B && a < N && b0 + j != 0) spec[(a << m) + b0 + j] = tile[tx][r];
+    // streaming stores: the final spectrum must not evict the slab from the caches
+    if (j < B && a < N && b0 + j != 0) __builtin_nontemporal_store(tile[tx][r], &spec[(a << m) + b0 + j]);
   }
 }
 
