@@ -277,16 +277,18 @@ def bench_extra(torch, B, inputs, dev):
     out["16x16_perm_spectrum_a"] = single(inputs.workload_16x16()["perm"], 16, 16, 2, reps=2)
     # component criteria (balancedness, correlation immunity, autocorrelation): two
     # transforms per mask in LDS
-    for n in (8, 12, 14):
+    for n in (8, 12, 14, 16):
         S = B.table_to_device(inputs.permutation(n, inputs.rng(inputs.SEED_BASE + 6)), n, device=dev)
         summ = torch.empty(8, dtype=torch.int32, device=dev)
         sptr = int(torch.cuda.current_stream(dev).cuda_stream)
+        cws = B.Workspace(B.sbox_criteria_workspace_bytes(n, n), dev)
 
         def crit():
-            st = B.sbox_criteria(S.data_ptr(), n, n, S.element_size(), summ.data_ptr(), 0, 0, 0, 0, sptr)
+            st = B.sbox_criteria_ex(S.data_ptr(), n, n, S.element_size(), summ.data_ptr(), 0, 0, 0, 0, cws.ptr,
+                                    cws.nbytes, sptr)
             if st != 0:
                 raise RuntimeError(B.last_error())
-        ms = _time_call(torch, crit, 3 if n == 14 else 10)
+        ms = _time_call(torch, crit, 1 if n == 16 else (3 if n == 14 else 10))
         coeffs = (1 << n) * ((1 << n) - 1)
         tops = 2 * n * coeffs / (ms * 1e-3) / 1e12
         out["criteria_%dx%d" % (n, n)] = {"ms": ms, "coeff_per_s": coeffs / (ms * 1e-3),

@@ -196,6 +196,19 @@ sbox_status sbox_criteria(const void* S, int n, int m, int s_elem_bytes, int32_t
                           int32_t* pcwt_per_b, void* stream);
 
 /*
+ * The same criteria up to n = 16 (1 <= n <= 16, 1 <= m <= 24, n + m <= 40).
+ * For n = 15, 16 the two transforms of each mask go through a slab of
+ * spectrum rows in the workspace (device, 256-byte aligned, at least
+ * sbox_criteria_workspace_bytes(n, m) bytes); for n <= 14 the workspace is
+ * not used and may be NULL.  No allocation, no host synchronisation.
+ */
+sbox_status sbox_criteria_ex(const void* S, int n, int m, int s_elem_bytes, int32_t* summary,
+                             int32_t* w0_per_b, int32_t* minwt_per_b, int32_t* acmax_per_b,
+                             int32_t* pcwt_per_b, void* workspace, size_t workspace_bytes,
+                             void* stream);
+size_t sbox_criteria_workspace_bytes(int n, int m);
+
+/*
  * Histogram of |W| over the nonzero masks: the distribution of the entries
  * of the Walsh matrix of Eq. 1 (equivalently of the linear approximation
  * table W/2), counted inside the transform, so the matrix is never stored:

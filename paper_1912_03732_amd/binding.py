@@ -55,7 +55,8 @@ class sbox_job(ctypes.Structure):
 # Every exported symbol of include/sbox_walsh.h.
 EXPORTS = ("sbox_walsh_nl", "sbox_walsh_nl_ex", "sbox_walsh_nl_workspace_bytes",
            "sbox_walsh_nl_batched", "sbox_batched_workspace_bytes", "sbox_plan_create",
-           "sbox_plan_launch", "sbox_plan_destroy", "sbox_criteria", "sbox_walsh_histogram",
+           "sbox_plan_launch", "sbox_plan_destroy", "sbox_criteria", "sbox_criteria_ex",
+           "sbox_criteria_workspace_bytes", "sbox_walsh_histogram",
            "sbox_walsh_histogram_workspace_bytes", "sbox_avalanche", "sbox_avalanche_workspace_bytes",
            "sbox_last_error", "sbox_version")
 
@@ -86,6 +87,10 @@ def load(path: str = LIB_PATH):
     lib.sbox_plan_destroy.restype = None
     lib.sbox_criteria.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, vp, vp]
     lib.sbox_criteria.restype = ctypes.c_int
+    lib.sbox_criteria_ex.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, vp, vp, sz, vp]
+    lib.sbox_criteria_ex.restype = ctypes.c_int
+    lib.sbox_criteria_workspace_bytes.argtypes = [i32, i32]
+    lib.sbox_criteria_workspace_bytes.restype = sz
     lib.sbox_walsh_histogram.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, sz, vp]
     lib.sbox_walsh_histogram.restype = ctypes.c_int
     lib.sbox_walsh_histogram_workspace_bytes.argtypes = [i32, i32]
@@ -157,6 +162,17 @@ def sbox_criteria(S: int, n: int, m: int, s_elem_bytes: int, summary: int, w0_pe
                   minwt_per_b: int, acmax_per_b: int, pcwt_per_b: int, stream: int) -> int:
     return load().sbox_criteria(S, n, m, s_elem_bytes, summary, w0_per_b, minwt_per_b, acmax_per_b,
                                 pcwt_per_b, stream)
+
+
+def sbox_criteria_ex(S: int, n: int, m: int, s_elem_bytes: int, summary: int, w0_per_b: int,
+                     minwt_per_b: int, acmax_per_b: int, pcwt_per_b: int, workspace: int, workspace_bytes: int,
+                     stream: int) -> int:
+    return load().sbox_criteria_ex(S, n, m, s_elem_bytes, summary, w0_per_b, minwt_per_b, acmax_per_b,
+                                   pcwt_per_b, workspace, workspace_bytes, stream)
+
+
+def sbox_criteria_workspace_bytes(n: int, m: int) -> int:
+    return int(load().sbox_criteria_workspace_bytes(n, m))
 
 
 def sbox_walsh_histogram(S: int, n: int, m: int, s_elem_bytes: int, hist: int, maxabs_per_b: int, nl: int,
@@ -347,7 +363,7 @@ CRITERIA_FIELDS = ("nl", "unbalanced", "ci_order", "resiliency", "abs_indicator"
 
 def criteria(S, n: int, m: int, *, per_mask: bool = True, stream=None):
     """Balancedness, correlation immunity / resiliency and autocorrelation
-    criteria of every nonzero component (n <= 14).  Returns (summary dict,
+    criteria of every nonzero component (n <= 16).  Returns (summary dict,
     dict of per-mask tensors w0, minwt, acmax, pcwt or None)."""
     torch = _torch()
     if not isinstance(S, torch.Tensor) or not S.is_cuda:
@@ -358,8 +374,10 @@ def criteria(S, n: int, m: int, *, per_mask: bool = True, stream=None):
     arrs = {k: torch.empty(1 << m, dtype=torch.int32, device=dev) for k in ("w0", "minwt", "acmax", "pcwt")} \
         if per_mask else None
     ptr = (lambda k: arrs[k].data_ptr()) if arrs else (lambda k: 0)
-    _check(sbox_criteria(S.data_ptr(), n, m, S.element_size(), summ.data_ptr(), ptr("w0"), ptr("minwt"),
-                         ptr("acmax"), ptr("pcwt"), _stream(torch, stream)))
+    ws = Workspace(sbox_criteria_workspace_bytes(n, m), dev) if n >= 15 else None
+    _check(sbox_criteria_ex(S.data_ptr(), n, m, S.element_size(), summ.data_ptr(), ptr("w0"), ptr("minwt"),
+                            ptr("acmax"), ptr("pcwt"), ws.ptr if ws else 0, ws.nbytes if ws else 0,
+                            _stream(torch, stream)))
     torch.cuda.synchronize(dev)
     v = summ.cpu().tolist()
     return {k: int(v[i]) for i, k in enumerate(CRITERIA_FIELDS)}, arrs

@@ -953,13 +953,135 @@ sbox_status sbox_walsh_nl_batched(const sbox_job* jobs, int32_t count, void* wor
   return launch_batch(L, workspace, st);
 }
 
-sbox_status sbox_criteria(const void* S, int n, int m, int s_elem_bytes, int32_t* summary, int32_t* w0_per_b,
-                          int32_t* minwt_per_b, int32_t* acmax_per_b, int32_t* pcwt_per_b, void* stream) {
-  if (n < 1 || n > 14 || m < 1 || m > 24)
-    return fail(SBOX_ERR_UNSUPPORTED, "criteria need 1<=n<=14 and 1<=m<=24 (n=%d m=%d)", n, m);
+size_t sbox_criteria_workspace_bytes(int n, int m) {
+  if (n < 1 || n > 16 || m < 1 || m > 24 || n + m > 40) return 0;
+  if (n <= 14) return 256;  // unused
+  return kQueueBytes + f_bytes(n, m) + slab_bytes(n, m);
+}
+
+namespace {
+// n = 15, 16: slabs of spectrum rows, see k_crit_rows_pre / k_crit_rows_post.
+sbox_status criteria_large(const void* S, int n, int m, int eb, int32_t* summary, int32_t* w0, int32_t* minwt,
+                           int32_t* acmax, int32_t* pcwt, void* ws, hipStream_t st) {
+  int cus = 0;
+  sbox_status s = device_info(&cus);
+  if (s) return s;
+  int* queue = reinterpret_cast<int*>(ws);
+  uint32_t* F = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(ws) + kQueueBytes);
+  int32_t* slab = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(ws) + kQueueBytes + f_bytes(n, m));
+  const int nwords = 1 << (n - 5);
+  {
+    const void* S_ = S;
+    int n_ = n, m_ = m, nw_ = nwords;
+    uint32_t* F_ = F;
+    void* args[] = {(void*)&S_, &n_, &m_, &F_, &nw_};
+    const void* fn = eb == 1 ? (const void*)&k_bitslice<1> : eb == 2 ? (const void*)&k_bitslice<2>
+                                                                    : (const void*)&k_bitslice<4>;
+    s = launch(fn, dim3((nwords + 255) / 256), dim3(256), args, st);
+    if (s) return s;
+  }
+  JobDesc jd{};
+  jd.S = S;
+  jd.F = F;
+  jd.nl = summary;  // the transform's running NL minimum lands in summary[0]
+  jd.n = n;
+  jd.m = m;
+  jd.nwords = nwords;
+  jd.s_elem_bytes = eb;
+  jd.wscale = wscale_of(SBOX_SPECTRUM_B_MAJOR);
+  {
+    // queue counters (and summary[0] = 2^(n-1) again; jd.spec is null: no row written)
+    const JobDesc* nulljobs = nullptr;
+    int one = 1, nq = 64, lay = 0;
+    void* args[] = {(void*)&nulljobs, &jd, &one, &queue, &nq, &lay};
+    s = launch((const void*)&k_init_jobs, dim3(1), dim3(256), args, st);
+    if (s) return s;
+  }
+  const int p = default_split(n);
+  KFn fn = lookup_kernel(n, p, kStoreB);
+  if (!fn) return fail(SBOX_ERR_INVALID_ARG, "no kernel for n=%d", n);
+  int occ = 1;
+  s = occupancy((const void*)fn, &occ);
+  if (s) return s;
+  const int groups = kWG >> (n - p);
+  const long long rows = slab_rows(n, m);
+  const int grid_cap = occ * cus;
+  int chunk = 1;
+  pick_chunk(rows, groups, grid_cap, 0, &chunk);
+  const long long per_item = (long long)groups * chunk;
+  const long long M = 1LL << m;
+  int qi = 1;
+  for (long long b0 = 0; b0 < M; b0 += rows, ++qi) {
+    if (qi >= 64) {
+      int* q = queue + 1;
+      long long cnt = 63;
+      void* za[] = {&q, &cnt};
+      s = launch((const void*)&k_zero, dim3(1), dim3(256), za, st);
+      if (s) return s;
+      qi = 1;
+    }
+    // rows b0 .. b0 + rows - 1 of W into the slab (Gray block inverse_gray(b0 / rows), as for a-major)
+    KParams kp{};
+    kp.job0 = jd;
+    kp.job0.spec = slab;
+    kp.njobs = 1;
+    kp.chunk = chunk;
+    kp.queue = queue + qi;
+    kp.kbase = inverse_gray(b0 / rows) * rows;
+    kp.kcount = rows;
+    kp.row0 = b0;
+    kp.rows = rows;
+    kp.total_items = (rows + per_item - 1) / per_item;
+    const int grid = (int)std::min<long long>(grid_cap, kp.total_items);
+    void* args[] = {&kp};
+    s = launch((const void*)fn, dim3(grid), dim3(kWG), args, st);
+    if (s) return s;
+    const unsigned nrows = (unsigned)std::min(rows, M - b0);
+    {
+      int32_t* sl = slab;
+      int n_ = n;
+      long long b0_ = b0, M_ = M;
+      void* a2[] = {&sl, &n_, &b0_, &M_, &summary, &w0, &minwt};
+      s = launch((const void*)&k_crit_rows_pre, dim3(nrows), dim3(256), a2, st);
+      if (s) return s;
+    }
+    for (int lo = 0; lo < n;) {
+      const int cwlog = std::min(lo, 6);
+      const int R = std::min(n - lo, 12 - cwlog);
+      int32_t* d = slab;
+      int mlog = n, lo_ = lo, R_ = R, cw = cwlog;
+      void* a3[] = {&d, &mlog, &lo_, &R_, &cw};
+      s = launch((const void*)&k_fwht_pass, dim3((unsigned)((long long)nrows << (n - R - cwlog))), dim3(256), a3, st);
+      if (s) return s;
+      lo += R;
+    }
+    {
+      const int32_t* sl = slab;
+      int n_ = n;
+      long long b0_ = b0, M_ = M;
+      void* a4[] = {(void*)&sl, &n_, &b0_, &M_, &summary, &acmax, &pcwt};
+      s = launch((const void*)&k_crit_rows_post, dim3(nrows), dim3(256), a4, st);
+      if (s) return s;
+    }
+  }
+  return SBOX_OK;
+}
+}  // namespace
+
+sbox_status sbox_criteria_ex(const void* S, int n, int m, int s_elem_bytes, int32_t* summary, int32_t* w0_per_b,
+                             int32_t* minwt_per_b, int32_t* acmax_per_b, int32_t* pcwt_per_b, void* workspace,
+                             size_t workspace_bytes, void* stream) {
+  if (n < 1 || n > 16 || m < 1 || m > 24 || n + m > 40)
+    return fail(SBOX_ERR_UNSUPPORTED, "criteria need 1<=n<=16, 1<=m<=24, n+m<=40 (n=%d m=%d)", n, m);
   if (!S || !summary) return fail(SBOX_ERR_INVALID_ARG, "S or summary is null");
   if (s_elem_bytes != 1 && s_elem_bytes != 2 && s_elem_bytes != 4)
     return fail(SBOX_ERR_INVALID_ARG, "s_elem_bytes must be 1, 2 or 4 (got %d)", s_elem_bytes);
+  if (n >= 15) {
+    const size_t need = sbox_criteria_workspace_bytes(n, m);
+    if (!workspace) return fail(SBOX_ERR_WORKSPACE, "workspace is null (need %zu bytes)", need);
+    if (reinterpret_cast<uintptr_t>(workspace) & 255) return fail(SBOX_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+    if (workspace_bytes < need) return fail(SBOX_ERR_WORKSPACE, "workspace of %zu bytes, need %zu", workspace_bytes, need);
+  }
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   int cus = 0;
   sbox_status s = device_info(&cus);
@@ -969,6 +1091,13 @@ sbox_status sbox_criteria(const void* S, int n, int m, int s_elem_bytes, int32_t
     void* args[] = {&summary, &n_, &w0_per_b, &minwt_per_b, &acmax_per_b, &pcwt_per_b};
     s = launch((const void*)&k_criteria_init, dim3(1), dim3(64), args, st);
     if (s) return s;
+  }
+  if (n >= 15) {
+    s = criteria_large(S, n, m, s_elem_bytes, summary, w0_per_b, minwt_per_b, acmax_per_b, pcwt_per_b, workspace,
+                       st);
+    if (s) return s;
+    void* args[] = {&summary};
+    return launch((const void*)&k_criteria_finish, dim3(1), dim3(64), args, st);
   }
   const void* fn = s_elem_bytes == 1 ? (const void*)&k_criteria<1>
                  : s_elem_bytes == 2 ? (const void*)&k_criteria<2> : (const void*)&k_criteria<4>;
@@ -993,6 +1122,15 @@ sbox_status sbox_criteria(const void* S, int n, int m, int s_elem_bytes, int32_t
   }
   void* args[] = {&summary};
   return launch((const void*)&k_criteria_finish, dim3(1), dim3(64), args, st);
+}
+
+sbox_status sbox_criteria(const void* S, int n, int m, int s_elem_bytes, int32_t* summary, int32_t* w0_per_b,
+                          int32_t* minwt_per_b, int32_t* acmax_per_b, int32_t* pcwt_per_b, void* stream) {
+  if (n < 1 || n > 14 || m < 1 || m > 24)
+    return fail(SBOX_ERR_UNSUPPORTED, "criteria need 1<=n<=14 and 1<=m<=24 without a workspace (n=%d m=%d); "
+                "sbox_criteria_ex takes n = 15, 16", n, m);
+  return sbox_criteria_ex(S, n, m, s_elem_bytes, summary, w0_per_b, minwt_per_b, acmax_per_b, pcwt_per_b, nullptr,
+                          0, stream);
 }
 
 struct sbox_plan {

@@ -1297,6 +1297,63 @@ __global__ __launch_bounds__(256) void k_criteria(const CritParams p) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Criteria of large boxes (n = 15, 16): the spectrum rows of a block of masks
+// are first written into a slab (b-major, W as int32, by the store-mode
+// transform), then one workgroup per row takes W(0, b) and the smallest
+// nonzero weight and squares (W/2) in place, the slab rows get the second
+// transform (k_fwht_pass), and one workgroup per row reads the
+// autocorrelation V(d) = 2^(n-2) r(d).  Parseval bounds every partial sum of
+// the second transform by sum_a (W/2)^2 = 4^(n-1) < 2^31: int32 is exact.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_crit_rows_pre(int32_t* slab, int n, long long b0, long long M,
+                                                       int32_t* crit, int32_t* w0, int32_t* minwt) {
+  __shared__ int red[4];
+  const long long b = b0 + blockIdx.x;
+  if (b == 0 || b >= M) return;  // block-uniform
+  int32_t* row = slab + ((long long)blockIdx.x << n);
+  const int N = 1 << n;
+  int mw = n + 1, w00 = 0;
+  for (int a = threadIdx.x; a < N; a += blockDim.x) {
+    const int v = row[a];
+    if (a == 0) w00 = v;
+    else if (v != 0) mw = min(mw, __builtin_popcount(a));
+    const int hv = v / 2;  // every W is even
+    row[a] = hv * hv;
+  }
+  mw = block_reduce<false>(mw, red);
+  if (threadIdx.x == 0) {
+    if (w0) w0[b] = w00;
+    if (minwt) minwt[b] = mw;
+    if (w00 != 0) atomicAdd(&crit[1], 1);
+    atomicMin(&crit[2], mw);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_crit_rows_post(const int32_t* slab, int n, long long b0, long long M,
+                                                        int32_t* crit, int32_t* acmax, int32_t* pcwt) {
+  __shared__ int red[4];
+  const long long b = b0 + blockIdx.x;
+  if (b == 0 || b >= M) return;
+  const int32_t* row = slab + ((long long)blockIdx.x << n);
+  const int N = 1 << n;
+  int ac = 0, pw = n + 1;
+  for (int d = threadIdx.x; d < N; d += blockDim.x) {
+    if (d == 0) continue;
+    const int r = row[d] >> (n - 2);  // V(d) = 2^(n-2) r(d), exactly
+    ac = max(ac, r < 0 ? -r : r);
+    if (r != 0) pw = min(pw, __builtin_popcount(d));
+  }
+  ac = block_reduce<true>(ac, red);
+  pw = block_reduce<false>(pw, red);
+  if (threadIdx.x == 0) {
+    if (acmax) acmax[b] = ac;
+    if (pcwt) pcwt[b] = pw;
+    atomicMax(&crit[4], ac);
+    atomicMin(&crit[5], pw);
+  }
+}
+
 // crit[] start values; per-mask outputs at b = 0 are defined as 0.
 __global__ void k_criteria_init(int32_t* crit, int n, int32_t* w0, int32_t* minwt, int32_t* acmax, int32_t* pcwt) {
   if (threadIdx.x == 0) {

@@ -170,3 +170,28 @@ def test_avalanche_workspace_query(lib):
     assert B.sbox_avalanche_workspace_bytes(24, 16) == 24 * 65536 * 4
     assert B.sbox_avalanche_workspace_bytes(8, 21) == 0
     assert B.sbox_avalanche_workspace_bytes(0, 4) == 0
+
+
+@pytest.mark.parametrize("args,status", [
+    (dict(n=17), B.SBOX_ERR_UNSUPPORTED),
+    (dict(n=16, m=25), B.SBOX_ERR_UNSUPPORTED),
+    (dict(S=0), B.SBOX_ERR_INVALID_ARG),
+    (dict(summary=0), B.SBOX_ERR_INVALID_ARG),
+    (dict(eb=3), B.SBOX_ERR_INVALID_ARG),
+    (dict(ws=0), B.SBOX_ERR_WORKSPACE),
+    (dict(ws_bytes=4096), B.SBOX_ERR_WORKSPACE),
+    (dict(ws=4096 + 16), B.SBOX_ERR_INVALID_ARG),
+])
+def test_criteria_ex_rejects_invalid_arguments(lib, args, status):
+    a = dict(S=4096, n=16, m=4, eb=2, summary=8192, ws=4096, ws_bytes=1 << 30)
+    a.update(args)
+    assert B.sbox_criteria_ex(a["S"], a["n"], a["m"], a["eb"], a["summary"], 0, 0, 0, 0, a["ws"], a["ws_bytes"],
+                              0) == status
+    assert B.sbox_last_error() != ""
+
+
+def test_criteria_without_workspace_stops_at_14(lib):
+    assert B.sbox_criteria(4096, 15, 4, 2, 8192, 0, 0, 0, 0, 0) == B.SBOX_ERR_UNSUPPORTED
+    assert B.sbox_criteria_workspace_bytes(16, 16) > (1 << 28)
+    assert B.sbox_criteria_workspace_bytes(14, 8) == 256
+    assert B.sbox_criteria_workspace_bytes(17, 4) == 0
