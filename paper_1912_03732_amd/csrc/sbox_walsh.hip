@@ -228,7 +228,11 @@ int mode_of(int layout) { return layout == 1 ? kStoreB : (layout == 2 ? kStoreA 
 // a-major output of a large spectrum (n <= 16, n + m >= 24): rows of a block
 // of masks go through a b-major slab that a tiled transpose turns into columns.
 bool use_slab(int n, int m, int layout) { return layout == 2 && n <= 16 && n >= 6 && n + m >= 24; }
-long long slab_rows(int n, int m) { return std::min(1LL << m, std::max(64LL, (1LL << 26) >> n)); }
+// slab of 2^SBW_SLAB_LOG int32 (256 MiB by default)
+#ifndef SBW_SLAB_LOG
+#define SBW_SLAB_LOG 26
+#endif
+long long slab_rows(int n, int m) { return std::min(1LL << m, std::max(64LL, (1LL << SBW_SLAB_LOG) >> n)); }
 size_t slab_bytes(int n, int m) { return align256((size_t)slab_rows(n, m) << n) * 4; }
 
 // Chunk and grid for a kernel with `groups` thread groups per workgroup over
