@@ -8,7 +8,10 @@ workspace are resident in HBM before timing starts.
 
 Prints one JSON line (rank 0, N = 1) with the throughput in Walsh
 coefficients per second, the roofline of the dominant kernel and the CPU
-oracle's rate on a bounded sample of the same workload.
+oracle's rate on a bounded sample of the same workload.  Unless --quick is
+given, the line also carries the batched workload (4096 uneven boxes in one
+planned launch against a loop of single-box calls) and the other workloads
+(each with its own roofline fraction) under "batched" and "extra".
 """
 from __future__ import annotations
 
@@ -43,16 +46,20 @@ def parse():
     ap.add_argument("--cpu-sample-masks", type=int, default=32768,
                     help="masks of the 16x16 box the CPU oracle is timed on")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
-    ap.add_argument("--batched", action="store_true", help="also time the mixed 4096-box batch")
+    ap.add_argument("--quick", action="store_true", help="the headline workload only (no batch, no extras)")
+    ap.add_argument("--batched", action="store_true", help="time the mixed 4096-box batch (default unless --quick)")
     ap.add_argument("--serving", action="store_true", help="also run the Poisson serving rate sweep")
     ap.add_argument("--serving-count", type=int, default=5000, help="requests per rate in the sweep")
-    ap.add_argument("--extra", action="store_true",
+    ap.add_argument("--extra", action="store_true",  # default unless --quick
                     help="also time the other workloads (8x8, 20x16, 16x20, 12x12 slice, 16x16 spectrum)")
     ap.add_argument("--variant", type=int, default=0, choices=(0, 1, 2),
                     help="butterfly engine for the 16x16 kernel: 0 library default, 1 VALU, 2 matrix cores")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters) and exit")
-    return ap.parse_args()
+    args = ap.parse_args()
+    if not args.quick:
+        args.batched = args.extra = True
+    return args
 
 
 # The fused 16x16 kernel each butterfly engine launches, and the file holding
@@ -65,21 +72,37 @@ def parse():
 KERNELS = {1: ("k_walsh<16,8,0>", "k_walsh_16x16_traffic.json", "i16", PEAK_PK16_TOPS),
            2: ("k_walsh_mfma16<4>", "k_walsh_mfma16_16x16_traffic.json", "f16", PEAK_MFMA_BUTTERFLY_TOPS)}
 DEFAULT_VARIANT = 2
+# Where each kernel's source starts and which function ends it: the counters
+# stay valid while the shared definitions before the first kernel and this
+# section are unchanged.
+KERNEL_SECTIONS = {1: ("// Main fused kernel", "void k_walsh(const KParams kp)"),
+                   2: ("// n = 16, max mode, matrix-core variant.", "void k_walsh_mfma16(const KParams kp)")}
 
 
-def measured_traffic(fname):
-    """HBM bytes per dispatch of the fused 16x16 kernel from the committed
-    rocprofv3 FETCH_SIZE / WRITE_SIZE runs, or None if the kernel source has
-    changed since they were taken."""
+def kernel_source_digest(variant):
+    """SHA-256 (16 hex digits) of the shared prefix of walsh_kernels.hpp and
+    of the section holding the kernel of this engine."""
     import hashlib
+    with open(os.path.join(ROOT, "paper_1912_03732_amd", "csrc", "walsh_kernels.hpp")) as f:
+        text = f.read()
+    start, func = KERNEL_SECTIONS[variant]
+    prefix = text[:text.index("// Main fused kernel")]
+    i = text.index(start)
+    j = text.index("\n}\n", text.index(func, i)) + 3
+    return hashlib.sha256((prefix + text[i:j]).encode()).hexdigest()[:16]
+
+
+def measured_traffic(fname, variant):
+    """HBM bytes per dispatch of the fused 16x16 kernel from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE runs, or None if the kernel's source has
+    changed since they were taken."""
     try:
         with open(os.path.join(ROOT, "profiles", fname)) as f:
             rec = json.load(f)
-        with open(os.path.join(ROOT, "paper_1912_03732_amd", "csrc", "walsh_kernels.hpp"), "rb") as f:
-            sha = hashlib.sha256(f.read()).hexdigest()[:16]
+        digest = kernel_source_digest(variant)
     except (OSError, ValueError):
         return None
-    return rec["traffic_bytes_per_dispatch"] if rec.get("kernel_source_sha256_16") == sha else None
+    return rec["traffic_bytes_per_dispatch"] if rec.get("kernel_source_sha256_16") == digest else None
 
 
 def host_cores() -> int:
@@ -136,7 +159,8 @@ def main():
     sptr = int(stream.cuda_stream)
 
     tuning = B.sbox_tuning(0, 0, 0, args.variant) if args.variant else None
-    kname, tfile, dtype, peak = KERNELS[args.variant or DEFAULT_VARIANT]
+    variant = args.variant or DEFAULT_VARIANT
+    kname, tfile, dtype, peak = KERNELS[variant]
 
     def step():
         st = B.sbox_walsh_nl_ex(S.data_ptr(), n, m, 2, mx.data_ptr(), nl.data_ptr(), 0, 0,
@@ -185,7 +209,7 @@ def main():
         # achieved: n add/subs per coefficient over the HIP-event time of the
         # step (the fused kernel is ~99 % of it; bit-slicing and init the rest)
         "roofline": {"bound": "alu", "achieved": achieved_tops, "peak": peak, "unit": "TOP/s",
-                     "frac": achieved_tops / peak, "traffic": measured_traffic(tfile),
+                     "frac": achieved_tops / peak, "traffic": measured_traffic(tfile, variant),
                      "kernel": kname, "event_ms_per_step": ev_mean,
                      "int32_valu_peak": PEAK_INT32_TOPS,
                      "int32_valu_frac": achieved_tops / PEAK_INT32_TOPS,
