@@ -363,3 +363,22 @@ def test_matrix_core_many_masks_sampled(n, m):
     assert np.array_equal(mx[masks], oracle.maxabs_for_masks(S, n, m, masks, nthreads=NT))
     assert mx[0] == 1 << n and np.all(mx[1:] >= 1 << (n // 2))
     assert nl == (1 << (n - 1)) - int(mx[1:].max()) // 2
+
+
+@pytest.mark.parametrize("n,m", [(24, 1), (23, 2), (4, 24), (1, 24)])
+def test_extreme_sizes_full(n, m):
+    """The size limits: n = 24 (the block path, 2^8 blocks of 2^16) and
+    m = 24 (16.7 million masks), bit-exact on every mask."""
+    check_against_oracle(table(n, m, 17000 + n + m), n, m, nthreads=NT)
+
+
+def test_largest_box_sampled():
+    """n + m = 40 at n = 16 (2^40 coefficients on the matrix-core engine):
+    sampled masks against the oracle, NL from the per-mask maxima."""
+    n, m = 16, 24
+    S = table(n, m, 17100)
+    nl, mx, _ = gpu_nl(S, n, m)
+    g = inputs.rng(17101)
+    masks = np.unique(np.concatenate([[1, (1 << m) - 1, 1 << 23, 0x5A5A5A], g.integers(1, 1 << m, 40)]))
+    assert np.array_equal(mx[masks], oracle.maxabs_for_masks(S, n, m, masks, nthreads=NT))
+    assert mx[0] == 1 << n and nl == (1 << 15) - int(mx[1:].max()) // 2
