@@ -960,11 +960,11 @@ sbox_status sbox_walsh_nl_batched(const sbox_job* jobs, int32_t count, void* wor
 size_t sbox_criteria_workspace_bytes(int n, int m) {
   if (n < 1 || n > 16 || m < 1 || m > 24 || n + m > 40) return 0;
   if (n <= 14) return 256;  // unused
-  return kQueueBytes + f_bytes(n, m) + slab_bytes(n, m);
+  return kQueueBytes + f_bytes(n, m) + slab_bytes(n, m) + 4 * align256((size_t)4 << m);
 }
 
 namespace {
-// n = 15, 16: slabs of spectrum rows, see k_crit_rows_pre / k_crit_rows_post.
+// n = 15, 16: slabs of spectrum rows, see k_crit_pass_a / k_crit_pass_b.
 sbox_status criteria_large(const void* S, int n, int m, int eb, int32_t* summary, int32_t* w0, int32_t* minwt,
                            int32_t* acmax, int32_t* pcwt, void* ws, hipStream_t st) {
   int cus = 0;
@@ -1014,6 +1014,21 @@ sbox_status criteria_large(const void* S, int n, int m, int eb, int32_t* summary
   pick_chunk(rows, groups, grid_cap, 0, &chunk);
   const long long per_item = (long long)groups * chunk;
   const long long M = 1LL << m;
+  CritLarge cl{};
+  {
+    char* p = reinterpret_cast<char*>(slab) + slab_bytes(n, m);
+    const size_t arr = align256((size_t)4 << m);
+    cl.w0 = reinterpret_cast<int32_t*>(p);
+    cl.mw = reinterpret_cast<int32_t*>(p + arr);
+    cl.ac = reinterpret_cast<int32_t*>(p + 2 * arr);
+    cl.pw = reinterpret_cast<int32_t*>(p + 3 * arr);
+    long long M_ = M;
+    int n_ = n;
+    void* af[] = {&M_, &n_, &cl};
+    s = launch((const void*)&k_crit_fill, dim3((unsigned)std::min<long long>(1024, (M + 255) / 256)), dim3(256), af,
+               st);
+    if (s) return s;
+  }
   int qi = 1;
   for (long long b0 = 0; b0 < M; b0 += rows, ++qi) {
     if (qi >= 64) {
@@ -1045,30 +1060,23 @@ sbox_status criteria_large(const void* S, int n, int m, int eb, int32_t* summary
       int32_t* sl = slab;
       int n_ = n;
       long long b0_ = b0, M_ = M;
-      void* a2[] = {&sl, &n_, &b0_, &M_, &summary, &w0, &minwt};
-      s = launch((const void*)&k_crit_rows_pre, dim3(nrows), dim3(256), a2, st);
+      void* a2[] = {&sl, &n_, &b0_, &M_, &cl};
+      s = launch((const void*)&k_crit_pass_a, dim3(nrows << (n - 12)), dim3(256), a2, st);
       if (s) return s;
-    }
-    for (int lo = 0; lo < n;) {
-      const int cwlog = std::min(lo, 6);
-      const int R = std::min(n - lo, 12 - cwlog);
-      int32_t* d = slab;
-      int mlog = n, lo_ = lo, R_ = R, cw = cwlog;
-      void* a3[] = {&d, &mlog, &lo_, &R_, &cw};
-      s = launch((const void*)&k_fwht_pass, dim3((unsigned)((long long)nrows << (n - R - cwlog))), dim3(256), a3, st);
-      if (s) return s;
-      lo += R;
     }
     {
       const int32_t* sl = slab;
       int n_ = n;
       long long b0_ = b0, M_ = M;
-      void* a4[] = {(void*)&sl, &n_, &b0_, &M_, &summary, &acmax, &pcwt};
-      s = launch((const void*)&k_crit_rows_post, dim3(nrows), dim3(256), a4, st);
+      void* a4[] = {(void*)&sl, &n_, &b0_, &M_, &cl};
+      s = launch((const void*)&k_crit_pass_b, dim3(nrows * 64), dim3(256), a4, st);
       if (s) return s;
     }
   }
-  return SBOX_OK;
+  long long M_ = M;
+  void* ar[] = {&M_, &cl, &summary, &w0, &minwt, &acmax, &pcwt};
+  return launch((const void*)&k_crit_reduce, dim3((unsigned)std::min<long long>(256, (M + 255) / 256)), dim3(256), ar,
+                st);
 }
 }  // namespace
 

@@ -1300,55 +1300,144 @@ __global__ __launch_bounds__(256) void k_criteria(const CritParams p) {
 // ---------------------------------------------------------------------------
 // Criteria of large boxes (n = 15, 16): the spectrum rows of a block of masks
 // are first written into a slab (b-major, W as int32, by the store-mode
-// transform), then one workgroup per row takes W(0, b) and the smallest
-// nonzero weight and squares (W/2) in place, the slab rows get the second
-// transform (k_fwht_pass), and one workgroup per row reads the
-// autocorrelation V(d) = 2^(n-2) r(d).  Parseval bounds every partial sum of
-// the second transform by sum_a (W/2)^2 = 4^(n-1) < 2^31: int32 is exact.
+// transform); pass A takes W(0, b) and the smallest nonzero weight, squares
+// W/2 and runs the first 12 stages of the second transform; pass B runs the
+// rest and reduces the autocorrelation V(d) = 2^(n-2) r(d) without writing
+// it back.  Parseval bounds every partial sum of the second transform by
+// sum_a (W/2)^2 = 4^(n-1) < 2^31: int32 is exact.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_crit_rows_pre(int32_t* slab, int n, long long b0, long long M,
-                                                       int32_t* crit, int32_t* w0, int32_t* minwt) {
+// Per-mask values of the large path live in workspace arrays (w0, smallest
+// weight of a nonzero W, largest |r|, smallest weight of a nonzero r), so
+// that the many workgroups of one mask meet at that mask's slot and the
+// aggregates are formed once at the end (k_crit_reduce), not by atomics on
+// one address.
+struct CritLarge {
+  int32_t* w0;
+  int32_t* mw;
+  int32_t* ac;
+  int32_t* pw;
+};
+
+// Pass A, one workgroup per 4096-entry segment of a row (mask b = b0 + row):
+// W(0, b) and the smallest weight of a nonzero W in the segment, then
+// (W/2)^2 and the first 12 stages of the second transform, in LDS.
+__global__ __launch_bounds__(256) void k_crit_pass_a(int32_t* slab, int n, long long b0, long long M, CritLarge cl) {
+  __shared__ int32_t t[4096];
   __shared__ int red[4];
-  const long long b = b0 + blockIdx.x;
+  const int segs_log = n - 12;
+  const long long row = blockIdx.x >> segs_log;
+  const int seg = blockIdx.x & ((1 << segs_log) - 1);
+  const long long b = b0 + row;
   if (b == 0 || b >= M) return;  // block-uniform
-  int32_t* row = slab + ((long long)blockIdx.x << n);
-  const int N = 1 << n;
-  int mw = n + 1, w00 = 0;
-  for (int a = threadIdx.x; a < N; a += blockDim.x) {
-    const int v = row[a];
-    if (a == 0) w00 = v;
+  int32_t* base = slab + (row << n) + ((long long)seg << 12);
+  int mw = n + 1;
+  for (int e = threadIdx.x; e < 4096; e += blockDim.x) {
+    const int v = base[e];
+    const int a = (seg << 12) | e;
+    if (a == 0) cl.w0[b] = v;
     else if (v != 0) mw = min(mw, __builtin_popcount(a));
     const int hv = v / 2;  // every W is even
-    row[a] = hv * hv;
+    t[e] = hv * hv;
   }
-  mw = block_reduce<false>(mw, red);
-  if (threadIdx.x == 0) {
-    if (w0) w0[b] = w00;
-    if (minwt) minwt[b] = mw;
-    if (w00 != 0) atomicAdd(&crit[1], 1);
-    atomicMin(&crit[2], mw);
+  mw = block_reduce<false>(mw, red);  // its barrier also orders the LDS writes
+  if (threadIdx.x == 0 && mw <= n) atomicMin(&cl.mw[b], mw);
+  for (int sb = 0; sb < 12; ++sb) {
+    for (int e = threadIdx.x; e < 2048; e += blockDim.x) {
+      const int i0 = ((e >> sb) << (sb + 1)) | (e & ((1 << sb) - 1)), i1 = i0 | (1 << sb);
+      const int32_t u = t[i0], v = t[i1];
+      t[i0] = u + v;
+      t[i1] = u - v;
+    }
+    __syncthreads();
   }
+  for (int e = threadIdx.x; e < 4096; e += blockDim.x) base[e] = t[e];
 }
 
-__global__ __launch_bounds__(256) void k_crit_rows_post(const int32_t* slab, int n, long long b0, long long M,
-                                                        int32_t* crit, int32_t* acmax, int32_t* pcwt) {
+// Pass B: the remaining n - 12 stages over tiles of 2^(n-12) rows (stride
+// 4096) by 64 columns, then V(d) = 2^(n-2) r(d) reduced in place: the largest
+// |r(d)| and the smallest weight of a nonzero r(d) over d != 0.
+__global__ __launch_bounds__(256) void k_crit_pass_b(const int32_t* slab, int n, long long b0, long long M,
+                                                     CritLarge cl) {
+  __shared__ int32_t t[16 * 64];
   __shared__ int red[4];
-  const long long b = b0 + blockIdx.x;
+  const int R = n - 12;
+  const long long row = blockIdx.x >> 6;
+  const int colb = blockIdx.x & 63;
+  const long long b = b0 + row;
   if (b == 0 || b >= M) return;
-  const int32_t* row = slab + ((long long)blockIdx.x << n);
-  const int N = 1 << n;
+  const int32_t* base = slab + (row << n) + colb * 64;
+  const int TILE = 64 << R;
+  for (int e = threadIdx.x; e < TILE; e += blockDim.x) t[e] = base[((long long)(e >> 6) << 12) | (e & 63)];
+  __syncthreads();
+  for (int sb = 0; sb < R; ++sb) {
+    for (int e = threadIdx.x; e < TILE / 2; e += blockDim.x) {
+      const int col = e & 63, rr = e >> 6;
+      const int r0 = ((rr >> sb) << (sb + 1)) | (rr & ((1 << sb) - 1));
+      const int i0 = (r0 << 6) | col, i1 = ((r0 | (1 << sb)) << 6) | col;
+      const int32_t u = t[i0], v = t[i1];
+      t[i0] = u + v;
+      t[i1] = u - v;
+    }
+    __syncthreads();
+  }
   int ac = 0, pw = n + 1;
-  for (int d = threadIdx.x; d < N; d += blockDim.x) {
+  for (int e = threadIdx.x; e < TILE; e += blockDim.x) {
+    const int d = ((e >> 6) << 12) | (colb * 64) | (e & 63);
     if (d == 0) continue;
-    const int r = row[d] >> (n - 2);  // V(d) = 2^(n-2) r(d), exactly
+    const int r = t[e] >> (n - 2);  // exact
     ac = max(ac, r < 0 ? -r : r);
     if (r != 0) pw = min(pw, __builtin_popcount(d));
   }
   ac = block_reduce<true>(ac, red);
   pw = block_reduce<false>(pw, red);
   if (threadIdx.x == 0) {
-    if (acmax) acmax[b] = ac;
-    if (pcwt) pcwt[b] = pw;
+    if (ac > 0) atomicMax(&cl.ac[b], ac);
+    if (pw <= n) atomicMin(&cl.pw[b], pw);
+  }
+}
+
+// Slots start at their identities: 0 for the largest |r|, n + 1 for the
+// smallest weights.
+__global__ __launch_bounds__(256) void k_crit_fill(long long M, int n, CritLarge cl) {
+  for (long long b = blockIdx.x * (long long)blockDim.x + threadIdx.x; b < M; b += (long long)gridDim.x * blockDim.x) {
+    cl.w0[b] = 0;
+    cl.mw[b] = n + 1;
+    cl.ac[b] = 0;
+    cl.pw[b] = n + 1;
+  }
+}
+
+// Aggregates over b = 1 .. M - 1 (unbalanced count, smallest weights,
+// largest |r|) into crit[], and the optional per-mask outputs.
+__global__ __launch_bounds__(256) void k_crit_reduce(long long M, CritLarge cl, int32_t* crit, int32_t* w0,
+                                                     int32_t* minwt, int32_t* acmax, int32_t* pcwt) {
+  __shared__ int red[4];
+  int unb = 0, mw = 0x7fffffff, ac = 0, pw = 0x7fffffff;
+  for (long long b = 1 + blockIdx.x * (long long)blockDim.x + threadIdx.x; b < M;
+       b += (long long)gridDim.x * blockDim.x) {
+    const int v0 = cl.w0[b], m0 = cl.mw[b], a0 = cl.ac[b], p0 = cl.pw[b];
+    unb += v0 != 0;
+    mw = min(mw, m0);
+    ac = max(ac, a0);
+    pw = min(pw, p0);
+    if (w0) w0[b] = v0;
+    if (minwt) minwt[b] = m0;
+    if (acmax) acmax[b] = a0;
+    if (pcwt) pcwt[b] = p0;
+  }
+  // block sums and extremes, then one atomic each per workgroup
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) unb += __shfl_xor(unb, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = unb;
+  __syncthreads();
+  unb = red[0] + red[1] + red[2] + red[3];
+  __syncthreads();
+  mw = block_reduce<false>(mw, red);
+  ac = block_reduce<true>(ac, red);
+  pw = block_reduce<false>(pw, red);
+  if (threadIdx.x == 0) {
+    if (unb) atomicAdd(&crit[1], unb);
+    atomicMin(&crit[2], mw);
     atomicMax(&crit[4], ac);
     atomicMin(&crit[5], pw);
   }
