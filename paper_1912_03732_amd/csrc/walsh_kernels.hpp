@@ -1255,6 +1255,8 @@ __global__ __launch_bounds__(256) void k_criteria(const CritParams p) {
   const int n = p.n;
   const int N = 1 << n;
   const long long M = 1LL << p.m;
+  // this workgroup's share of the aggregates (thread 0), added once at the end
+  int g_nl = N >> 1, g_unb = 0, g_mw = n + 1, g_ac = 0, g_pw = n + 1;
   for (long long b = blockIdx.x + 1; b < M; b += gridDim.x) {
     for (int x = threadIdx.x; x < N; x += blockDim.x)
       buf[x] = (__builtin_popcount((uint32_t)b & load_entry<EB>(p.S, x)) & 1) ? -1 : 1;
@@ -1287,13 +1289,20 @@ __global__ __launch_bounds__(256) void k_criteria(const CritParams p) {
       if (p.minwt) p.minwt[b] = mw;
       if (p.acmax) p.acmax[b] = ac;
       if (p.pcwt) p.pcwt[b] = pw;
-      atomicMin(&p.crit[0], (N - mx) >> 1);
-      if (w0 != 0) atomicAdd(&p.crit[1], 1);
-      atomicMin(&p.crit[2], mw);
-      atomicMax(&p.crit[4], ac);
-      atomicMin(&p.crit[5], pw);
+      g_nl = min(g_nl, (N - mx) >> 1);
+      g_unb += w0 != 0;
+      g_mw = min(g_mw, mw);
+      g_ac = max(g_ac, ac);
+      g_pw = min(g_pw, pw);
     }
     __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    atomicMin(&p.crit[0], g_nl);
+    if (g_unb) atomicAdd(&p.crit[1], g_unb);
+    atomicMin(&p.crit[2], g_mw);
+    atomicMax(&p.crit[4], g_ac);
+    atomicMin(&p.crit[5], g_pw);
   }
 }
 
