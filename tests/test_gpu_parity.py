@@ -382,3 +382,54 @@ def test_largest_box_sampled():
     masks = np.unique(np.concatenate([[1, (1 << m) - 1, 1 << 23, 0x5A5A5A], g.integers(1, 1 << m, 40)]))
     assert np.array_equal(mx[masks], oracle.maxabs_for_masks(S, n, m, masks, nthreads=NT))
     assert mx[0] == 1 << n and nl == (1 << 15) - int(mx[1:].max()) // 2
+
+
+@pytest.mark.parametrize("n,m,spectrum", [(8, 8, "b"), (12, 10, None), (16, 4, None)])
+def test_single_call_graph_replay(n, m, spectrum):
+    """sbox_walsh_nl_ex with a caller workspace is captured into a HIP graph
+    and replayed: every replay (with eager work and synchronisation between)
+    equals the eager call, and the replay reads the table at replay time."""
+    import torch
+    S = table(n, m, 17200 + n)
+    t = dev_table(S, m)
+    layout = {None: 0, "b": B.SPECTRUM_B_MAJOR}[spectrum]
+    ws = B.Workspace(B.sbox_walsh_nl_workspace_bytes(n, m, layout))
+    nl = torch.empty(1, dtype=torch.int32, device="cuda")
+    mx = torch.empty(1 << m, dtype=torch.int32, device="cuda")
+    spec = torch.empty(1 << (n + m), dtype=torch.int32, device="cuda") if layout else None
+
+    def call():
+        st = B.sbox_walsh_nl_ex(t.data_ptr(), n, m, t.element_size(), mx.data_ptr(), nl.data_ptr(),
+                                spec.data_ptr() if spec is not None else 0, layout, ws.ptr, ws.nbytes, None,
+                                int(torch.cuda.current_stream().cuda_stream))
+        assert st == B.SBOX_OK, B.last_error()
+    call()
+    torch.cuda.synchronize()
+    ref = (int(nl.item()), mx.cpu().numpy().copy(), spec.cpu().numpy().copy() if spec is not None else None)
+    assert ref[0] == oracle.walsh_nl(S, n, m)[0]
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        call()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        call()
+    for rep in range(4):
+        nl.fill_(-1)
+        mx.zero_()
+        if spec is not None:
+            spec.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert int(nl.item()) == ref[0], rep
+        assert np.array_equal(mx.cpu().numpy(), ref[1]), rep
+        if spec is not None:
+            assert np.array_equal(spec.cpu().numpy(), ref[2]), rep
+    new = table(n, m, 17300 + n)
+    t.copy_(dev_table(new, m))
+    g.replay()
+    torch.cuda.synchronize()
+    assert int(nl.item()) == oracle.walsh_nl(new, n, m)[0]
