@@ -188,6 +188,30 @@ __device__ __forceinline__ void load_words(uint32_t (&G)[NW], const uint32_t* p,
 }
 
 // ---------------------------------------------------------------------------
+// Maximum (or minimum) over groups of W consecutive lanes, W a power of two:
+// DPP moves inside each row of 16 lanes (quad swaps, half-row and row
+// mirrors) leave the group's result in all its lanes; 32 lanes add one
+// cross-row shuffle, a whole wave combines its four rows through readlane
+// (uniform result).  Replaces chains of dependent LDS permutes.
+// ---------------------------------------------------------------------------
+template <bool IS_MAX>
+__device__ __forceinline__ int pick(int a, int b) { return IS_MAX ? max(a, b) : min(a, b); }
+
+template <int W, bool IS_MAX = true>
+__device__ __forceinline__ int group_reduce(int v) {
+  if constexpr (W >= 2) v = pick<IS_MAX>(v, __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false));   // quad 1,0,3,2
+  if constexpr (W >= 4) v = pick<IS_MAX>(v, __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false));   // quad 2,3,0,1
+  if constexpr (W >= 8) v = pick<IS_MAX>(v, __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, false));  // half-row mirror
+  if constexpr (W >= 16) v = pick<IS_MAX>(v, __builtin_amdgcn_mov_dpp(v, 0x140, 0xF, 0xF, false)); // row mirror
+  if constexpr (W == 32) v = pick<IS_MAX>(v, __shfl_xor(v, 16, 64));
+  if constexpr (W == 64)
+    v = pick<IS_MAX>(pick<IS_MAX>(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
+                     pick<IS_MAX>(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
+  return v;
+}
+__device__ __forceinline__ int wave_max(int v) { return group_reduce<64, true>(v); }
+
+// ---------------------------------------------------------------------------
 // Main fused kernel, n <= 16 (MODE kBlock: one 2^16 block of a larger n).
 // ---------------------------------------------------------------------------
 constexpr int kLdsStride = kWG + 1;  // padded LDS row (odd number of words)
@@ -522,8 +546,7 @@ __global__ __launch_bounds__(kWG, (min_blocks<N, P_, MODE>())) void k_walsh(cons
       // ---- per-mask maximum over the thread group
       if constexpr (Q >= 1) {
         constexpr int W = (Q < 6) ? (1 << Q) : 64;
-#pragma unroll
-        for (int o = 1; o < W; o <<= 1) mx = max(mx, __shfl_xor(mx, o, 64));
+        mx = group_reduce<W>(mx);
       }
       if constexpr (Q >= 7) {
         if (lane == 0) red[tid >> 6] = mx;
@@ -767,9 +790,7 @@ __global__ __launch_bounds__(kWG, ROUNDS) void k_walsh_mfma16(const KParams kp) 
             }
         }
       }
-      int mx = (int)fmaxf(m0, m1);
-#pragma unroll
-      for (int o = 1; o < 64; o <<= 1) mx = max(mx, __shfl_xor(mx, o, 64));
+      const int mx = wave_max((int)fmaxf(m0, m1));
       if (lane == 0) red[(step & 63) * 4 + wave] = mx;
       if ((step & 63) == 63 || step == C - 1) {
         // every 64 masks and at the item's end: wave 0 finishes the masks
@@ -932,9 +953,7 @@ __global__ __launch_bounds__(kWG, 4) void k_walsh_mfma12(const KParams kp) {
         m0 = fmaxf(fmaxf(m0, fabsf(e0[2])), fabsf(e1[2]));
         m1 = fmaxf(fmaxf(m1, fabsf(e0[3])), fabsf(e1[3]));
       }
-      int mx = (int)fmaxf(m0, m1);
-#pragma unroll
-      for (int o = 1; o < 64; o <<= 1) mx = max(mx, __shfl_xor(mx, o, 64));
+      const int mx = wave_max((int)fmaxf(m0, m1));
       if (lane == 0 && k != 0) {
         if (jd.maxabs) jd.maxabs[(uint32_t)gray(k)] = 2 * mx;
         runmin = min(runmin, (1 << (n - 1)) - mx);
@@ -1117,9 +1136,7 @@ __global__ __launch_bounds__(kWG, 2) void k_walsh_big(const BigParams bp) {
             lov = min(lov, min(min(s0, d0), min(s1, d1)));
           }
         }
-        int mx = max(hiv, -lov);
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) mx = max(mx, __shfl_xor(mx, o, 64));
+        int mx = wave_max(max(hiv, -lov));
         if (lane == 0) red[tid >> 6] = mx;
         __syncthreads();
         mx = max(max(red[0], red[1]), max(red[2], red[3]));
@@ -1235,11 +1252,7 @@ __device__ __forceinline__ void lds_fwht(int32_t* buf, int n) {
 
 template <bool IS_MAX>
 __device__ __forceinline__ int block_reduce(int v, int* red) {
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int w = __shfl_xor(v, o, 64);
-    v = IS_MAX ? max(v, w) : min(v, w);
-  }
+  v = group_reduce<64, IS_MAX>(v);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
   int r = red[0];
