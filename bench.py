@@ -116,7 +116,21 @@ def host_cores() -> int:
     return max(1, n)
 
 
+def host_cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(S, n, m, sample_masks):
+    """The oracle on the host: all usable cores (threads over masks, the
+    paper's partition of the masks among threads), then one core on a
+    sixteenth of the sample."""
     import numpy as np
     import oracle
     cores = host_cores()
@@ -125,9 +139,16 @@ def cpu_baseline(S, n, m, sample_masks):
     t0 = time.perf_counter()
     oracle.maxabs_for_masks(S, n, m, masks, nthreads=cores)
     dt = time.perf_counter() - t0
+    one = masks[:max(1, masks.size // 16)]
+    t0 = time.perf_counter()
+    oracle.maxabs_for_masks(S, n, m, one, nthreads=1)
+    dt1 = time.perf_counter() - t0
     return {"value": masks.size * (1 << n) / dt, "unit": "coeff/s", "cores": cores, "kind": "oracle",
             "sample": "masks b=1..%d of the same %dx%d box (%.1f s wall on %d threads)"
-                      % (masks.size, n, m, dt, cores)}
+                      % (masks.size, n, m, dt, cores),
+            "single_core": {"value": one.size * (1 << n) / dt1, "unit": "coeff/s",
+                            "sample": "masks b=1..%d on 1 thread (%.1f s wall)" % (one.size, dt1)},
+            "cpu_model": host_cpu_model()}
 
 
 def main():
