@@ -361,10 +361,12 @@ class Plan:
 CRITERIA_FIELDS = ("nl", "unbalanced", "ci_order", "resiliency", "abs_indicator", "pc_order")
 
 
-def criteria(S, n: int, m: int, *, per_mask: bool = True, stream=None):
+def criteria(S, n: int, m: int, *, per_mask: bool = True, workspace: bool = True, stream=None):
     """Balancedness, correlation immunity / resiliency and autocorrelation
     criteria of every nonzero component (n <= 16).  Returns (summary dict,
-    dict of per-mask tensors w0, minwt, acmax, pcwt or None)."""
+    dict of per-mask tensors w0, minwt, acmax, pcwt or None).  With
+    workspace=False (n <= 14 only) the library runs its LDS kernel instead of
+    the register-blocked one that a workspace selects."""
     torch = _torch()
     if not isinstance(S, torch.Tensor) or not S.is_cuda:
         raise TypeError("S must be a device tensor")
@@ -374,7 +376,7 @@ def criteria(S, n: int, m: int, *, per_mask: bool = True, stream=None):
     arrs = {k: torch.empty(1 << m, dtype=torch.int32, device=dev) for k in ("w0", "minwt", "acmax", "pcwt")} \
         if per_mask else None
     ptr = (lambda k: arrs[k].data_ptr()) if arrs else (lambda k: 0)
-    ws = Workspace(sbox_criteria_workspace_bytes(n, m), dev) if n >= 15 else None
+    ws = Workspace(sbox_criteria_workspace_bytes(n, m), dev) if (workspace or n >= 15) else None
     _check(sbox_criteria_ex(S.data_ptr(), n, m, S.element_size(), summ.data_ptr(), ptr("w0"), ptr("minwt"),
                             ptr("acmax"), ptr("pcwt"), ws.ptr if ws else 0, ws.nbytes if ws else 0,
                             _stream(torch, stream)))

@@ -959,11 +959,64 @@ sbox_status sbox_walsh_nl_batched(const sbox_job* jobs, int32_t count, void* wor
 
 size_t sbox_criteria_workspace_bytes(int n, int m) {
   if (n < 1 || n > 16 || m < 1 || m > 24 || n + m > 40) return 0;
-  if (n <= 14) return 256;  // unused
+  if (n <= 4) return 256;  // unused
+  if (n <= 14) return f_bytes(n, m) + (size_t)kCritRegMaxGrid * 8 * 4;
   return kQueueBytes + f_bytes(n, m) + slab_bytes(n, m) + 4 * align256((size_t)4 << m);
 }
 
 namespace {
+// 5 <= n <= 14 with a workspace: bit-sliced words, then the register-blocked
+// kernel (one group of lanes per mask, both transforms without leaving the CU).
+sbox_status criteria_reg(const void* S, int n, int m, int eb, int32_t* summary, int32_t* w0, int32_t* minwt,
+                         int32_t* acmax, int32_t* pcwt, void* ws, hipStream_t st) {
+  int cus = 0;
+  sbox_status s = device_info(&cus);
+  if (s) return s;
+  uint32_t* F = reinterpret_cast<uint32_t*>(ws);
+  const int nwords = 1 << (n - 5);
+  {
+    const void* S_ = S;
+    int n_ = n, m_ = m, nw_ = nwords;
+    void* args[] = {(void*)&S_, &n_, &m_, &F, &nw_};
+    const void* fn = eb == 1 ? (const void*)&k_bitslice<1> : eb == 2 ? (const void*)&k_bitslice<2>
+                                                                    : (const void*)&k_bitslice<4>;
+    s = launch(fn, dim3((nwords + 255) / 256), dim3(256), args, st);
+    if (s) return s;
+  }
+  static const void* const fns[] = {
+      (const void*)&k_crit_reg<5>,  (const void*)&k_crit_reg<6>,  (const void*)&k_crit_reg<7>,
+      (const void*)&k_crit_reg<8>,  (const void*)&k_crit_reg<9>,  (const void*)&k_crit_reg<10>,
+      (const void*)&k_crit_reg<11>, (const void*)&k_crit_reg<12>, (const void*)&k_crit_reg<13>,
+      (const void*)&k_crit_reg<14>};
+  const void* fn = fns[n - 5];
+  const int gpb = 256 >> (n - crit_reg_rb(n));  // groups (masks in flight) per workgroup
+  int occ = 1;
+  s = occupancy(fn, &occ);
+  if (s) return s;
+  const long long masks = (1LL << m) - 1;
+  const long long cap = std::min<long long>((long long)std::max(1, occ) * cus, kCritRegMaxGrid) * gpb;
+  CritRegParams cp{};
+  cp.F = F;
+  cp.m = m;
+  cp.chunk = (masks + cap - 1) / cap;
+  cp.part = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(ws) + f_bytes(n, m));
+  cp.w0 = w0;
+  cp.minwt = minwt;
+  cp.acmax = acmax;
+  cp.pcwt = pcwt;
+  const long long groups = (masks + cp.chunk - 1) / cp.chunk;
+  const int grid = (int)((groups + gpb - 1) / gpb);  // <= kCritRegMaxGrid
+  {
+    void* args[] = {&cp};
+    s = launch(fn, dim3((unsigned)grid), dim3(256), args, st);
+    if (s) return s;
+  }
+  const int32_t* part = cp.part;
+  int nwg = grid;
+  void* args[] = {(void*)&part, &nwg, &summary};
+  return launch((const void*)&k_crit_reg_finish, dim3(1), dim3(256), args, st);
+}
+
 // n = 15, 16: slabs of spectrum rows, see k_crit_pass_a / k_crit_pass_b.
 sbox_status criteria_large(const void* S, int n, int m, int eb, int32_t* summary, int32_t* w0, int32_t* minwt,
                            int32_t* acmax, int32_t* pcwt, void* ws, hipStream_t st) {
@@ -1088,7 +1141,10 @@ sbox_status sbox_criteria_ex(const void* S, int n, int m, int s_elem_bytes, int3
   if (!S || !summary) return fail(SBOX_ERR_INVALID_ARG, "S or summary is null");
   if (s_elem_bytes != 1 && s_elem_bytes != 2 && s_elem_bytes != 4)
     return fail(SBOX_ERR_INVALID_ARG, "s_elem_bytes must be 1, 2 or 4 (got %d)", s_elem_bytes);
-  if (n >= 15) {
+  // n >= 15 needs a workspace; for 5 <= n <= 14 one selects the register-blocked
+  // kernel (without one, the LDS kernel runs)
+  const bool use_ws = n >= 15 || (n >= 5 && workspace != nullptr);
+  if (use_ws) {
     const size_t need = sbox_criteria_workspace_bytes(n, m);
     if (!workspace) return fail(SBOX_ERR_WORKSPACE, "workspace is null (need %zu bytes)", need);
     if (reinterpret_cast<uintptr_t>(workspace) & 255) return fail(SBOX_ERR_INVALID_ARG, "workspace not 256-byte aligned");
@@ -1104,9 +1160,12 @@ sbox_status sbox_criteria_ex(const void* S, int n, int m, int s_elem_bytes, int3
     s = launch((const void*)&k_criteria_init, dim3(1), dim3(64), args, st);
     if (s) return s;
   }
-  if (n >= 15) {
-    s = criteria_large(S, n, m, s_elem_bytes, summary, w0_per_b, minwt_per_b, acmax_per_b, pcwt_per_b, workspace,
-                       st);
+  if (use_ws) {
+    if (n <= 14)  // finishes the summary itself
+      return criteria_reg(S, n, m, s_elem_bytes, summary, w0_per_b, minwt_per_b, acmax_per_b, pcwt_per_b,
+                          workspace, st);
+    s = criteria_large(S, n, m, s_elem_bytes, summary, w0_per_b, minwt_per_b, acmax_per_b, pcwt_per_b,
+                       workspace, st);
     if (s) return s;
     void* args[] = {&summary};
     return launch((const void*)&k_criteria_finish, dim3(1), dim3(64), args, st);

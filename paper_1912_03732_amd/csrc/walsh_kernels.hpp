@@ -1250,6 +1250,17 @@ __device__ __forceinline__ void lds_fwht(int32_t* buf, int n) {
   }
 }
 
+__device__ __forceinline__ int block_sum(int v, int* red) {
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  int r = red[0];
+  for (int i = 1; i < (int)(blockDim.x >> 6); ++i) r += red[i];
+  __syncthreads();
+  return r;
+}
+
 template <bool IS_MAX>
 __device__ __forceinline__ int block_reduce(int v, int* red) {
   v = group_reduce<64, IS_MAX>(v);
@@ -1316,6 +1327,339 @@ __global__ __launch_bounds__(256) void k_criteria(const CritParams p) {
     atomicMin(&p.crit[2], g_mw);
     atomicMax(&p.crit[4], g_ac);
     atomicMin(&p.crit[5], g_pw);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Component criteria, register-blocked (5 <= n <= 14, needs the bit-sliced
+// words F).  A group of GL lanes owns one mask at a time and each lane holds
+// R = 2^RB int32 values (RB = max(5, ceil(n/2)) up to n = 12, RB = 6 above).
+// Layouts of the 2^n entries (register j of lane l):
+//   A: entry (l << RB) | j            bits 0..RB-1 in registers
+//   B: entry (j << LB) | l            bits LB..n-1 in registers (n <= 12,
+//                                     LB = n - RB)
+//   for n = 13, 14 (RB = 6), between them
+//   M: entry (l_hi << 12) | (j << 6) | l_lo, l = (l_hi, l_lo): bits 6..11
+//   and C: entry (j << (n-6)) | l     bits n-6..n-1
+// The transforms are products of commuting per-bit stages, so each runs the
+// stages of whatever bits its current layout holds in registers:
+//   first transform A -> (M ->) B/C: popcount stages over bits 0..4 (bias -16:
+//     the values are u = -W/2 from the start), then the register stages;
+//   v = u^2 = (W/2)^2 (24-bit multiply, |u| <= 2^13);
+//   second transform back to A, giving V(d) = 2^(n-2) r(d).
+// Exchanges go through LDS rows of R + 4 words holding 64 (or R) consecutive
+// entries: layout A moves 16-byte quads of its own row (the padding puts the
+// rows of consecutive lanes on different banks), the other layouts single
+// words at (lane + a constant per register), conflict-free.
+// Reductions: max v gives max|W|; for the smallest weight of a nonzero value
+// the registers are OR-ed by the weight of their index (a compile-time
+// constant) and the lane adds the weight of its own bits.
+// ---------------------------------------------------------------------------
+constexpr int kCritRegMaxGrid = 4096;  // workgroups (one slot of partial aggregates each)
+
+struct CritRegParams {
+  const uint32_t* F;  // [m][2^(n-5)] bit-sliced words
+  int m;
+  long long chunk;    // Gray indices per group
+  int32_t* part;      // [gridDim.x][8] per-workgroup aggregates (nl, unbalanced, minwt, acmax, pcwt)
+  int32_t* w0;
+  int32_t* minwt;
+  int32_t* acmax;
+  int32_t* pcwt;
+};
+
+// register bits per lane of the register-blocked criteria kernel (host and device)
+__host__ __device__ constexpr int crit_reg_rb(int n) { return n > 12 ? 6 : ((n + 1) / 2 > 5 ? (n + 1) / 2 : 5); }
+
+template <int N>
+struct CritShape {
+  static constexpr bool THREE = N > 12;         // layouts A, M, C
+  static constexpr int RB = crit_reg_rb(N);
+  static constexpr int LB = N - RB;
+  static constexpr int R = 1 << RB;
+  static constexpr int GL = 1 << LB;            // lanes per group
+  static constexpr int WPL = R / 32;
+  static constexpr int GPB = 256 / GL;          // groups per workgroup
+  static constexpr int ROW = R + 4;             // padded LDS row (words)
+  static constexpr int GWORDS = GL * ROW;       // LDS words per group
+};
+
+// Butterflies of one register bit over an array of R values.
+template <int R, int BIT>
+__device__ __forceinline__ void reg_stage(int32_t* v) {
+#pragma unroll
+  for (int j = 0; j < R; ++j)
+    if (!(j & (1 << BIT))) {
+      const int32_t a = v[j], b = v[j | (1 << BIT)];
+      v[j] = a + b;
+      v[j | (1 << BIT)] = a - b;
+    }
+}
+template <int R, int LO, int HI>
+__device__ __forceinline__ void reg_stages(int32_t* v) {
+  if constexpr (LO < HI) {
+    reg_stage<R, LO>(v);
+    reg_stages<R, LO + 1, HI>(v);
+  }
+}
+
+// Smallest class c (0..C) whose OR-accumulator is nonzero, skipping class 0
+// when skip0; 99 if none.
+template <int C>
+__device__ __forceinline__ int first_class(const uint32_t* acc, bool skip0) {
+  int c = 99;
+#pragma unroll
+  for (int k = C; k >= 1; --k) c = acc[k] ? k : c;
+  return (!skip0 && acc[0]) ? 0 : c;
+}
+
+template <int GL>
+__device__ __forceinline__ void group_sync() {
+  if constexpr (GL > 64) {
+    __syncthreads();
+  } else {
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+// Reduction over the GL lanes of a group; GL > 64 spans GL / 64 waves that
+// meet in `xr` (one int per wave).
+template <int GL, bool IS_MAX>
+__device__ __forceinline__ int crit_group_reduce(int v, int* xr, int l) {
+  if constexpr (GL <= 64) {
+    return group_reduce<GL, IS_MAX>(v);
+  } else {
+    v = group_reduce<64, IS_MAX>(v);
+    if ((l & 63) == 0) xr[l >> 6] = v;
+    __syncthreads();
+    int r = xr[0];
+#pragma unroll
+    for (int w = 1; w < GL / 64; ++w) r = IS_MAX ? max(r, xr[w]) : min(r, xr[w]);
+    __syncthreads();
+    return r;
+  }
+}
+
+// Layout A side of an exchange: the lane's own row, 16-byte quads.
+template <int R, int ROW>
+__device__ __forceinline__ void put_rows(int32_t* buf, int l, const int32_t* v) {
+#pragma unroll
+  for (int q = 0; q < R / 4; ++q)
+    *reinterpret_cast<int4*>(buf + l * ROW + 4 * q) = make_int4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+}
+template <int R, int ROW>
+__device__ __forceinline__ void get_rows(const int32_t* buf, int l, int32_t* v) {
+#pragma unroll
+  for (int q = 0; q < R / 4; ++q) {
+    const int4 t = *reinterpret_cast<const int4*>(buf + l * ROW + 4 * q);
+    v[4 * q] = t.x;
+    v[4 * q + 1] = t.y;
+    v[4 * q + 2] = t.z;
+    v[4 * q + 3] = t.w;
+  }
+}
+template <int N>
+__global__ __launch_bounds__(256) void k_crit_reg(const CritRegParams p) {
+  using C = CritShape<N>;
+  constexpr bool THREE = C::THREE;
+  constexpr int RB = C::RB, LB = C::LB, R = C::R, GL = C::GL, WPL = C::WPL, GPB = C::GPB, ROW = C::ROW;
+  __shared__ __attribute__((aligned(16))) int32_t lds[GPB * C::GWORDS];
+  __shared__ int xr[GPB][4];
+  __shared__ int agg[GPB][5];
+  const int tid = threadIdx.x;
+  const int grp = tid / GL;
+  const int l = tid % GL;
+  int32_t* buf = lds + grp * C::GWORDS;
+  auto at = [](int e) { return (e >> RB) * ROW + (e & (R - 1)); };  // LDS word of entry e
+  const int nwords = 1 << (N - 5);
+  const long long kend = 1LL << p.m;
+  const long long kfirst = 1 + ((long long)blockIdx.x * GPB + grp) * p.chunk;
+  const int lw = __builtin_popcount(l);
+  // M layout: lane (l_hi, l_lo) = (l >> 6, l & 63) holds entry (l_hi << 12) | (j << 6) | l_lo
+  const int mbase = THREE ? at(((l >> 6) << 12) | (l & 63)) : 0;
+
+  // this group's share of the aggregates, folded per workgroup at the end
+  int g_nl = 1 << (N - 1), g_unb = 0, g_mw = N + 1, g_ac = 0, g_pw = N + 1;
+
+  uint32_t G[WPL], Fn[WPL];
+#pragma unroll
+  for (int t = 0; t < WPL; ++t) G[t] = Fn[t] = 0;
+  if (kfirst < kend) {
+    const long long gk = gray(kfirst);
+    for (int i = 0; i < p.m; ++i)
+      if ((gk >> i) & 1) {
+#pragma unroll
+        for (int t = 0; t < WPL; ++t) G[t] ^= p.F[(long long)i * nwords + l * WPL + t];
+      }
+  }
+  // every group runs the same number of steps (uniform barriers); steps past
+  // the last mask compute on stale words and write nothing
+  for (long long step = 0; step < p.chunk; ++step) {
+    const long long k = kfirst + step;
+    const bool valid = k < kend;
+    if (step > 0) {
+#pragma unroll
+      for (int t = 0; t < WPL; ++t) G[t] ^= Fn[t];
+    }
+    if (k + 1 < kend && step + 1 < p.chunk) {
+      const int i = __builtin_ctzll((unsigned long long)(k + 1));
+#pragma unroll
+      for (int t = 0; t < WPL; ++t) Fn[t] = p.F[(long long)i * nwords + l * WPL + t];
+    }
+    int32_t v[R];
+    // ---- first transform, layout A: popcounts (bits 0..4), then bits 5..RB-1
+#pragma unroll
+    for (int t = 0; t < WPL; ++t)
+#pragma unroll
+      for (int a = 0; a < 32; ++a) v[t * 32 + a] = (int32_t)__builtin_popcount(G[t] ^ walsh_mask(a)) - 16;
+    reg_stages<R, 5, RB>(v);
+    put_rows<R, ROW>(buf, l, v);
+    group_sync<GL>();
+    if constexpr (THREE) {
+      // ---- A -> M: bits 6..11
+#pragma unroll
+      for (int j = 0; j < R; ++j) v[j] = buf[mbase + j * ROW];
+      group_sync<GL>();
+      reg_stages<R, 0, 6>(v);
+#pragma unroll
+      for (int j = 0; j < R; ++j) buf[mbase + j * ROW] = v[j];
+      group_sync<GL>();
+      // ---- M -> C: bits 12..n-1 = register bits 18-n..5
+#pragma unroll
+      for (int j = 0; j < R; ++j) v[j] = buf[at((j << (N - 6)) | l)];
+      group_sync<GL>();
+      reg_stages<R, 18 - N, 6>(v);
+    } else {
+      // ---- A -> B: bits RB..n-1 = register bits RB-LB..RB-1
+#pragma unroll
+      for (int j = 0; j < R; ++j) v[j] = buf[at(j << LB) + l];
+      group_sync<GL>();
+      reg_stages<R, RB - LB, RB>(v);
+    }
+    // u = -W/2 at a = (j << LB) | l (both B and C)
+    const int w0 = -2 * v[0];  // W(0, b) (lane l = 0)
+    uint32_t ci[RB + 1];
+#pragma unroll
+    for (int c = 0; c <= RB; ++c) ci[c] = 0;
+    int mxsq = 0;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const int32_t s = __mul24(v[j], v[j]);
+      mxsq = max(mxsq, s);
+      ci[__builtin_popcount(j)] |= (uint32_t)s;
+      v[j] = s;
+    }
+    // ---- second transform: all register bits of B / C
+    reg_stages<R, 0, RB>(v);
+    if constexpr (THREE) {
+      // ---- C -> M: bits 6..n-7 = register bits 0..n-13
+#pragma unroll
+      for (int j = 0; j < R; ++j) buf[at((j << (N - 6)) | l)] = v[j];
+      group_sync<GL>();
+#pragma unroll
+      for (int j = 0; j < R; ++j) v[j] = buf[mbase + j * ROW];
+      group_sync<GL>();
+      reg_stages<R, 0, N - 12>(v);
+#pragma unroll
+      for (int j = 0; j < R; ++j) buf[mbase + j * ROW] = v[j];
+    } else {
+#pragma unroll
+      for (int j = 0; j < R; ++j) buf[at(j << LB) + l] = v[j];
+    }
+    group_sync<GL>();
+    get_rows<R, ROW>(buf, l, v);
+    group_sync<GL>();
+    // ---- layout A: the bits not yet done (0..LB-1, or 0..5); V(d) at d = (l << RB) | j
+    reg_stages<R, 0, THREE ? 6 : LB>(v);
+    if (l == 0) v[0] = 0;  // d = 0 is not a direction
+    uint32_t pc[RB + 1];
+#pragma unroll
+    for (int c = 0; c <= RB; ++c) pc[c] = 0;
+    int vmax = 0, vmin = 0;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      vmax = max(vmax, v[j]);
+      vmin = min(vmin, v[j]);
+      pc[__builtin_popcount(j)] |= (uint32_t)v[j];
+    }
+    // ---- per-lane results, then the group's
+    int mw = first_class<RB>(ci, l == 0) + lw;
+    int pw = first_class<RB>(pc, l == 0) + lw;
+    int ac = max(vmax, -vmin) >> (N - 2);  // |V| = 2^(n-2) |r|, exact
+    mxsq = crit_group_reduce<GL, true>(mxsq, xr[grp], l);
+    mw = crit_group_reduce<GL, false>(mw, xr[grp], l);
+    ac = crit_group_reduce<GL, true>(ac, xr[grp], l);
+    pw = crit_group_reduce<GL, false>(pw, xr[grp], l);
+    if (mw > N) mw = N + 1;
+    if (pw > N) pw = N + 1;
+    if (l == 0 && valid) {
+      const long long b = gray(k);
+      const int umax = (int)rintf(sqrtf((float)mxsq));  // mxsq is a perfect square <= 2^26
+      if (p.w0) p.w0[b] = w0;
+      if (p.minwt) p.minwt[b] = mw;
+      if (p.acmax) p.acmax[b] = ac;
+      if (p.pcwt) p.pcwt[b] = pw;
+      g_nl = min(g_nl, (1 << (N - 1)) - umax);
+      g_unb += w0 != 0;
+      g_mw = min(g_mw, mw);
+      g_ac = max(g_ac, ac);
+      g_pw = min(g_pw, pw);
+    }
+  }
+  // the workgroup's aggregates into its slot (no atomics on shared words:
+  // thousands of them from every workgroup serialise in L2)
+  if (l == 0) {
+    agg[grp][0] = g_nl;
+    agg[grp][1] = g_unb;
+    agg[grp][2] = g_mw;
+    agg[grp][3] = g_ac;
+    agg[grp][4] = g_pw;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int q = 1; q < GPB; ++q) {
+      g_nl = min(g_nl, agg[q][0]);
+      g_unb += agg[q][1];
+      g_mw = min(g_mw, agg[q][2]);
+      g_ac = max(g_ac, agg[q][3]);
+      g_pw = min(g_pw, agg[q][4]);
+    }
+    int32_t* o = p.part + 8 * blockIdx.x;
+    o[0] = g_nl;
+    o[1] = g_unb;
+    o[2] = g_mw;
+    o[3] = g_ac;
+    o[4] = g_pw;
+  }
+}
+
+// Aggregates of the register-blocked criteria kernel: the per-workgroup slots
+// folded into crit[] (which holds the start values), then the orders as in
+// k_criteria_finish.
+__global__ __launch_bounds__(256) void k_crit_reg_finish(const int32_t* part, int nwg, int32_t* crit) {
+  __shared__ int red[4];
+  int nl = 0x7fffffff, unb = 0, mw = 0x7fffffff, ac = 0, pw = 0x7fffffff;
+  for (int i = threadIdx.x; i < nwg; i += blockDim.x) {
+    const int32_t* o = part + 8 * i;
+    nl = min(nl, o[0]);
+    unb += o[1];
+    mw = min(mw, o[2]);
+    ac = max(ac, o[3]);
+    pw = min(pw, o[4]);
+  }
+  nl = block_reduce<false>(nl, red);
+  mw = block_reduce<false>(mw, red);
+  ac = block_reduce<true>(ac, red);
+  pw = block_reduce<false>(pw, red);
+  unb = block_sum(unb, red);
+  if (threadIdx.x == 0) {
+    crit[0] = min(crit[0], nl);
+    crit[1] += unb;
+    crit[2] = min(crit[2], mw) - 1;
+    crit[3] = crit[1] == 0 ? crit[2] : -1;
+    crit[4] = max(crit[4], ac);
+    crit[5] = min(crit[5], pw) - 1;
   }
 }
 

@@ -193,5 +193,17 @@ def test_criteria_ex_rejects_invalid_arguments(lib, args, status):
 def test_criteria_without_workspace_stops_at_14(lib):
     assert B.sbox_criteria(4096, 15, 4, 2, 8192, 0, 0, 0, 0, 0) == B.SBOX_ERR_UNSUPPORTED
     assert B.sbox_criteria_workspace_bytes(16, 16) > (1 << 28)
-    assert B.sbox_criteria_workspace_bytes(14, 8) == 256
+    # 5 <= n <= 14: the bit-sliced words (m x 2^(n-5) x 4 bytes, 256-aligned) of the register-blocked
+    # kernel and 4096 slots of 8 ints for its per-workgroup aggregates
+    assert B.sbox_criteria_workspace_bytes(14, 8) == 8 * 512 * 4 + 4096 * 32
+    assert B.sbox_criteria_workspace_bytes(5, 3) == 256 + 4096 * 32
+    assert B.sbox_criteria_workspace_bytes(4, 4) == 256
     assert B.sbox_criteria_workspace_bytes(17, 4) == 0
+
+
+def test_criteria_ex_small_n_workspace_checked_when_given(lib):
+    """For 5 <= n <= 14 a workspace is optional, but one that is passed must
+    be aligned and large enough."""
+    need = B.sbox_criteria_workspace_bytes(12, 8)
+    assert B.sbox_criteria_ex(4096, 12, 8, 1, 8192, 0, 0, 0, 0, 4096, need - 1, 0) == B.SBOX_ERR_WORKSPACE
+    assert B.sbox_criteria_ex(4096, 12, 8, 1, 8192, 0, 0, 0, 0, 4096 + 16, need, 0) == B.SBOX_ERR_INVALID_ARG
