@@ -197,10 +197,16 @@ sbox_status sbox_criteria(const void* S, int n, int m, int s_elem_bytes, int32_t
 
 /*
  * The same criteria up to n = 16 (1 <= n <= 16, 1 <= m <= 24, n + m <= 40).
- * For n = 15, 16 the two transforms of each mask go through a slab of
- * spectrum rows in the workspace (device, 256-byte aligned, at least
- * sbox_criteria_workspace_bytes(n, m) bytes); for n <= 14 the workspace is
- * not used and may be NULL.  No allocation, no host synchronisation.
+ * The workspace (device, 256-byte aligned, at least
+ * sbox_criteria_workspace_bytes(n, m) bytes) is required for n = 15, 16,
+ * where the two transforms of each mask go through a slab of spectrum rows.
+ * For 5 <= n <= 14 it is optional: given, it holds the bit-sliced table and
+ * per-workgroup partial aggregates of the register-blocked kernel (both
+ * transforms of a mask without leaving the compute unit, several times
+ * faster); NULL runs the same kernel as sbox_criteria.  A workspace that is
+ * given must meet the size and alignment above (else SBOX_ERR_WORKSPACE /
+ * SBOX_ERR_INVALID_ARG).  For n <= 4 it is not used.  No allocation, no
+ * host synchronisation.
  */
 sbox_status sbox_criteria_ex(const void* S, int n, int m, int s_elem_bytes, int32_t* summary,
                              int32_t* w0_per_b, int32_t* minwt_per_b, int32_t* acmax_per_b,
