@@ -960,7 +960,7 @@ sbox_status sbox_walsh_nl_batched(const sbox_job* jobs, int32_t count, void* wor
 size_t sbox_criteria_workspace_bytes(int n, int m) {
   if (n < 1 || n > 16 || m < 1 || m > 24 || n + m > 40) return 0;
   if (n <= 4) return 256;  // unused
-  if (n <= 14) return f_bytes(n, m) + (size_t)kCritRegMaxGrid * 8 * 4;
+  if (n <= 15) return f_bytes(n, m) + (size_t)kCritRegMaxGrid * 8 * 4;
   return kQueueBytes + f_bytes(n, m) + slab_bytes(n, m) + 4 * align256((size_t)4 << m);
 }
 
@@ -987,9 +987,10 @@ sbox_status criteria_reg(const void* S, int n, int m, int eb, int32_t* summary, 
       (const void*)&k_crit_reg<5>,  (const void*)&k_crit_reg<6>,  (const void*)&k_crit_reg<7>,
       (const void*)&k_crit_reg<8>,  (const void*)&k_crit_reg<9>,  (const void*)&k_crit_reg<10>,
       (const void*)&k_crit_reg<11>, (const void*)&k_crit_reg<12>, (const void*)&k_crit_reg<13>,
-      (const void*)&k_crit_reg<14>};
+      (const void*)&k_crit_reg<14>, (const void*)&k_crit_reg<15>};
   const void* fn = fns[n - 5];
-  const int gpb = 256 >> (n - crit_reg_rb(n));  // groups (masks in flight) per workgroup
+  const int wg = crit_reg_wg(n);
+  const int gpb = wg >> (n - crit_reg_rb(n));  // groups (masks in flight) per workgroup
   int occ = 1;
   s = occupancy(fn, &occ);
   if (s) return s;
@@ -1008,7 +1009,7 @@ sbox_status criteria_reg(const void* S, int n, int m, int eb, int32_t* summary, 
   const int grid = (int)((groups + gpb - 1) / gpb);  // <= kCritRegMaxGrid
   {
     void* args[] = {&cp};
-    s = launch(fn, dim3((unsigned)grid), dim3(256), args, st);
+    s = launch(fn, dim3((unsigned)grid), dim3(wg), args, st);
     if (s) return s;
   }
   const int32_t* part = cp.part;
@@ -1017,7 +1018,7 @@ sbox_status criteria_reg(const void* S, int n, int m, int eb, int32_t* summary, 
   return launch((const void*)&k_crit_reg_finish, dim3(1), dim3(256), args, st);
 }
 
-// n = 15, 16: slabs of spectrum rows, see k_crit_pass_a / k_crit_pass_b.
+// n = 16: slabs of spectrum rows, see k_crit_pass_a / k_crit_pass_b.
 sbox_status criteria_large(const void* S, int n, int m, int eb, int32_t* summary, int32_t* w0, int32_t* minwt,
                            int32_t* acmax, int32_t* pcwt, void* ws, hipStream_t st) {
   int cus = 0;
@@ -1161,7 +1162,7 @@ sbox_status sbox_criteria_ex(const void* S, int n, int m, int s_elem_bytes, int3
     if (s) return s;
   }
   if (use_ws) {
-    if (n <= 14)  // finishes the summary itself
+    if (n <= 15)  // finishes the summary itself
       return criteria_reg(S, n, m, s_elem_bytes, summary, w0_per_b, minwt_per_b, acmax_per_b, pcwt_per_b,
                           workspace, st);
     s = criteria_large(S, n, m, s_elem_bytes, summary, w0_per_b, minwt_per_b, acmax_per_b, pcwt_per_b,

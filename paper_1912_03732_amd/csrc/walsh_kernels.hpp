@@ -1331,21 +1331,23 @@ __global__ __launch_bounds__(256) void k_criteria(const CritParams p) {
 }
 
 // ---------------------------------------------------------------------------
-// Component criteria, register-blocked (5 <= n <= 14, needs the bit-sliced
+// Component criteria, register-blocked (5 <= n <= 15, needs the bit-sliced
 // words F).  A group of GL lanes owns one mask at a time and each lane holds
-// R = 2^RB int32 values (RB = max(5, ceil(n/2)) up to n = 12, RB = 6 above).
+// R = 2^RB int32 values (RB = max(5, ceil(n/2)) up to n = 12, RB = 6 above;
+// at n = 15 the group is a whole workgroup of 512 lanes, its 2^15 entries
+// filling 136 KiB of LDS at the exchanges).
 // Layouts of the 2^n entries (register j of lane l):
 //   A: entry (l << RB) | j            bits 0..RB-1 in registers
 //   B: entry (j << LB) | l            bits LB..n-1 in registers (n <= 12,
 //                                     LB = n - RB)
-//   for n = 13, 14 (RB = 6), between them
+//   for n = 13 .. 15 (RB = 6), between them
 //   M: entry (l_hi << 12) | (j << 6) | l_lo, l = (l_hi, l_lo): bits 6..11
 //   and C: entry (j << (n-6)) | l     bits n-6..n-1
 // The transforms are products of commuting per-bit stages, so each runs the
 // stages of whatever bits its current layout holds in registers:
 //   first transform A -> (M ->) B/C: popcount stages over bits 0..4 (bias -16:
 //     the values are u = -W/2 from the start), then the register stages;
-//   v = u^2 = (W/2)^2 (24-bit multiply, |u| <= 2^13);
+//   v = u^2 = (W/2)^2 (24-bit multiply, |u| <= 2^14);
 //   second transform back to A, giving V(d) = 2^(n-2) r(d).
 // Exchanges go through LDS rows of R + 4 words holding 64 (or R) consecutive
 // entries: layout A moves 16-byte quads of its own row (the padding puts the
@@ -1368,8 +1370,10 @@ struct CritRegParams {
   int32_t* pcwt;
 };
 
-// register bits per lane of the register-blocked criteria kernel (host and device)
+// register bits per lane of the register-blocked criteria kernel, and its
+// workgroup size (host and device)
 __host__ __device__ constexpr int crit_reg_rb(int n) { return n > 12 ? 6 : ((n + 1) / 2 > 5 ? (n + 1) / 2 : 5); }
+__host__ __device__ constexpr int crit_reg_wg(int n) { return (1 << (n - crit_reg_rb(n))) > 256 ? (1 << (n - crit_reg_rb(n))) : 256; }
 
 template <int N>
 struct CritShape {
@@ -1379,7 +1383,8 @@ struct CritShape {
   static constexpr int R = 1 << RB;
   static constexpr int GL = 1 << LB;            // lanes per group
   static constexpr int WPL = R / 32;
-  static constexpr int GPB = 256 / GL;          // groups per workgroup
+  static constexpr int WG = crit_reg_wg(N);     // threads per workgroup
+  static constexpr int GPB = WG / GL;           // groups per workgroup
   static constexpr int ROW = R + 4;             // padded LDS row (words)
   static constexpr int GWORDS = GL * ROW;       // LDS words per group
 };
@@ -1460,12 +1465,12 @@ __device__ __forceinline__ void get_rows(const int32_t* buf, int l, int32_t* v) 
   }
 }
 template <int N>
-__global__ __launch_bounds__(256) void k_crit_reg(const CritRegParams p) {
+__global__ __launch_bounds__(crit_reg_wg(N)) void k_crit_reg(const CritRegParams p) {
   using C = CritShape<N>;
   constexpr bool THREE = C::THREE;
   constexpr int RB = C::RB, LB = C::LB, R = C::R, GL = C::GL, WPL = C::WPL, GPB = C::GPB, ROW = C::ROW;
   __shared__ __attribute__((aligned(16))) int32_t lds[GPB * C::GWORDS];
-  __shared__ int xr[GPB][4];
+  __shared__ int xr[GPB][GL > 64 ? GL / 64 : 1];
   __shared__ int agg[GPB][5];
   const int tid = threadIdx.x;
   const int grp = tid / GL;
@@ -1595,7 +1600,7 @@ __global__ __launch_bounds__(256) void k_crit_reg(const CritRegParams p) {
     if (pw > N) pw = N + 1;
     if (l == 0 && valid) {
       const long long b = gray(k);
-      const int umax = (int)rintf(sqrtf((float)mxsq));  // mxsq is a perfect square <= 2^26
+      const int umax = (int)rintf(sqrtf((float)mxsq));  // mxsq is a perfect square <= 2^28
       if (p.w0) p.w0[b] = w0;
       if (p.minwt) p.minwt[b] = mw;
       if (p.acmax) p.acmax[b] = ac;

@@ -93,17 +93,45 @@ def test_criteria_inversion_and_nl_agree_with_fused_path():
     assert summ["nl"] == B.walsh_nl(dev_table(S, 12), 12, 12)[0]
 
 
-@pytest.mark.parametrize("n,m", [(15, 3), (16, 2), (16, 3)])
+@pytest.mark.parametrize("n,m", [(15, 3), (15, 4), (16, 2), (16, 3)])
 def test_criteria_large_random(n, m):
-    """n = 15, 16 go through the slab path (spectrum rows, squares, second
+    """n = 15 runs the register-blocked kernel with one 512-lane group per
+    workgroup; n = 16 the slab path (spectrum rows, squares, second
     transform, row reductions): bit-exact against the oracle."""
     _check(table(n, m, 12500 + n * m), n, m)
 
 
-def test_criteria_large_structured():
-    x = np.arange(1 << 16)
-    _check(np.bitwise_count(x.astype(np.uint64)).astype(np.uint32) & 1, 16, 1)  # parity: 15-resilient
-    _check(np.bitwise_count(((x & 255) & (x >> 8)).astype(np.uint64)).astype(np.uint32) & 1, 16, 1)  # bent
+@pytest.mark.parametrize("n", [15, 16])
+def test_criteria_large_structured(n):
+    x = np.arange(1 << n)
+    _check(np.bitwise_count(x.astype(np.uint64)).astype(np.uint32) & 1, n, 1)  # parity: (n-1)-resilient
+    h = n // 2
+    _check(np.bitwise_count(((x & ((1 << h) - 1)) & (x >> h)).astype(np.uint64)).astype(np.uint32) & 1, n, 1)
+    A = x ^ (x >> 5) ^ ((x & 7) << 9)  # linear, invertible: one nonzero W per mask
+    _check(A & 7, n, 3)
+
+
+def test_criteria_15x15_sampled():
+    """A 15 x 15 permutation, every mask through the kernel; per-mask values
+    on sampled masks against the oracle's transform column and definition,
+    the summary against the per-mask arrays and NL against the fused path."""
+    n = 15
+    S = inputs.permutation(n, inputs.rng(12800))
+    Sd = dev_table(S, n)
+    summ, per = B.criteria(Sd, n, n)
+    per = {k: v.cpu().numpy() for k, v in per.items()}
+    assert summ["nl"] == B.walsh_nl(Sd, n, n)[0]
+    assert summ["unbalanced"] == 0 and np.all(per["w0"][1:] == 0)
+    assert summ["abs_indicator"] == int(per["acmax"][1:].max())
+    assert summ["ci_order"] == int(per["minwt"][1:].min()) - 1
+    assert summ["pc_order"] == int(per["pcwt"][1:].min()) - 1
+    wts = np.bitwise_count(np.arange(1 << n).astype(np.uint64))
+    for b in [1, 0x7FFF]:
+        col = oracle.walsh_column(S, n, n, b)
+        assert per["minwt"][b] == int(wts[1:][col[1:] != 0].min())
+        r = oracle.autocorrelation(S, n, n, b)
+        assert per["acmax"][b] == int(np.abs(r[1:]).max())
+        assert per["pcwt"][b] == int(wts[1:][r[1:] != 0].min())
 
 
 def test_criteria_16x16_permutation():
