@@ -321,7 +321,7 @@ def bench_extra(torch, B, inputs, dev):
     out["16x16_perm_spectrum_b"] = single(inputs.workload_16x16()["perm"], 16, 16, 1, reps=2)
     out["16x16_perm_spectrum_a"] = single(inputs.workload_16x16()["perm"], 16, 16, 2, reps=2)
     # component criteria (balancedness, correlation immunity, autocorrelation): two
-    # transforms per mask in LDS
+    # int32 transforms per mask, register-blocked
     for n in (8, 12, 14, 16):
         S = B.table_to_device(inputs.permutation(n, inputs.rng(inputs.SEED_BASE + 6)), n, device=dev)
         summ = torch.empty(8, dtype=torch.int32, device=dev)
@@ -339,7 +339,7 @@ def bench_extra(torch, B, inputs, dev):
         out["criteria_%dx%d" % (n, n)] = {"ms": ms, "coeff_per_s": coeffs / (ms * 1e-3),
                                           "int_ops_per_s": 2 * n * coeffs / (ms * 1e-3),
                                           "summary": summ.cpu().tolist()[:6],
-                                          # two int32 transforms per mask through LDS
+                                          # two int32 transforms (n 2^n add/sub each) per mask
                                           "roofline": {"bound": "alu", "achieved": tops, "peak": PEAK_INT32_TOPS,
                                                        "unit": "TOP/s", "frac": tops / PEAK_INT32_TOPS}}
     # |W| histogram over all nonzero masks (fused into the transform)

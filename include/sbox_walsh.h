@@ -198,13 +198,13 @@ sbox_status sbox_criteria(const void* S, int n, int m, int s_elem_bytes, int32_t
 /*
  * The same criteria up to n = 16 (1 <= n <= 16, 1 <= m <= 24, n + m <= 40).
  * The workspace (device, 256-byte aligned, at least
- * sbox_criteria_workspace_bytes(n, m) bytes) is required for n = 15, 16,
- * where the two transforms of each mask go through a slab of spectrum rows.
- * For 5 <= n <= 14 it is optional: given, it holds the bit-sliced table and
- * per-workgroup partial aggregates of the register-blocked kernel (both
- * transforms of a mask without leaving the compute unit, several times
- * faster); NULL runs the same kernel as sbox_criteria.  A workspace that is
- * given must meet the size and alignment above (else SBOX_ERR_WORKSPACE /
+ * sbox_criteria_workspace_bytes(n, m) bytes: the bit-sliced table and one
+ * slot of partial aggregates per workgroup) selects the register-blocked
+ * kernel, which keeps both transforms of a mask on one compute unit (a
+ * whole 1024-lane workgroup per mask at n = 16).  It is required for
+ * n = 15, 16; for 5 <= n <= 14 it is optional and NULL runs the same kernel
+ * as sbox_criteria (several times slower).  A workspace that is given must
+ * meet the size and alignment above (else SBOX_ERR_WORKSPACE /
  * SBOX_ERR_INVALID_ARG).  For n <= 4 it is not used.  No allocation, no
  * host synchronisation.
  */

@@ -119,7 +119,9 @@ sbox_status device_info(int* cus) {
   return SBOX_OK;
 }
 
-sbox_status occupancy(const void* fn, int* blocks_per_cu) {
+// Resident workgroups of `block` threads per CU (each kernel is always
+// launched with one block size, so the kernel address keys the cache).
+sbox_status occupancy(const void* fn, int* blocks_per_cu, int block = kWG) {
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
   std::lock_guard<std::mutex> lk(g_dev_mu);
@@ -127,7 +129,7 @@ sbox_status occupancy(const void* fn, int* blocks_per_cu) {
   auto it = di.occ.find(fn);
   if (it == di.occ.end()) {
     int nb = 0;
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kWG, 0));
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, block, 0));
     if (nb < 1) nb = 1;
     it = di.occ.emplace(fn, nb).first;
   }
@@ -960,8 +962,7 @@ sbox_status sbox_walsh_nl_batched(const sbox_job* jobs, int32_t count, void* wor
 size_t sbox_criteria_workspace_bytes(int n, int m) {
   if (n < 1 || n > 16 || m < 1 || m > 24 || n + m > 40) return 0;
   if (n <= 4) return 256;  // unused
-  if (n <= 15) return f_bytes(n, m) + (size_t)kCritRegMaxGrid * 8 * 4;
-  return kQueueBytes + f_bytes(n, m) + slab_bytes(n, m) + 4 * align256((size_t)4 << m);
+  return f_bytes(n, m) + (size_t)kCritRegMaxGrid * 8 * 4;
 }
 
 namespace {
@@ -987,12 +988,12 @@ sbox_status criteria_reg(const void* S, int n, int m, int eb, int32_t* summary, 
       (const void*)&k_crit_reg<5>,  (const void*)&k_crit_reg<6>,  (const void*)&k_crit_reg<7>,
       (const void*)&k_crit_reg<8>,  (const void*)&k_crit_reg<9>,  (const void*)&k_crit_reg<10>,
       (const void*)&k_crit_reg<11>, (const void*)&k_crit_reg<12>, (const void*)&k_crit_reg<13>,
-      (const void*)&k_crit_reg<14>, (const void*)&k_crit_reg<15>};
+      (const void*)&k_crit_reg<14>, (const void*)&k_crit_reg<15>, (const void*)&k_crit_reg16};
   const void* fn = fns[n - 5];
   const int wg = crit_reg_wg(n);
   const int gpb = wg >> (n - crit_reg_rb(n));  // groups (masks in flight) per workgroup
   int occ = 1;
-  s = occupancy(fn, &occ);
+  s = occupancy(fn, &occ, wg);
   if (s) return s;
   const long long masks = (1LL << m) - 1;
   const long long cap = std::min<long long>((long long)std::max(1, occ) * cus, kCritRegMaxGrid) * gpb;
@@ -1018,120 +1019,6 @@ sbox_status criteria_reg(const void* S, int n, int m, int eb, int32_t* summary, 
   return launch((const void*)&k_crit_reg_finish, dim3(1), dim3(256), args, st);
 }
 
-// n = 16: slabs of spectrum rows, see k_crit_pass_a / k_crit_pass_b.
-sbox_status criteria_large(const void* S, int n, int m, int eb, int32_t* summary, int32_t* w0, int32_t* minwt,
-                           int32_t* acmax, int32_t* pcwt, void* ws, hipStream_t st) {
-  int cus = 0;
-  sbox_status s = device_info(&cus);
-  if (s) return s;
-  int* queue = reinterpret_cast<int*>(ws);
-  uint32_t* F = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(ws) + kQueueBytes);
-  int32_t* slab = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(ws) + kQueueBytes + f_bytes(n, m));
-  const int nwords = 1 << (n - 5);
-  {
-    const void* S_ = S;
-    int n_ = n, m_ = m, nw_ = nwords;
-    uint32_t* F_ = F;
-    void* args[] = {(void*)&S_, &n_, &m_, &F_, &nw_};
-    const void* fn = eb == 1 ? (const void*)&k_bitslice<1> : eb == 2 ? (const void*)&k_bitslice<2>
-                                                                    : (const void*)&k_bitslice<4>;
-    s = launch(fn, dim3((nwords + 255) / 256), dim3(256), args, st);
-    if (s) return s;
-  }
-  JobDesc jd{};
-  jd.S = S;
-  jd.F = F;
-  jd.nl = summary;  // the transform's running NL minimum lands in summary[0]
-  jd.n = n;
-  jd.m = m;
-  jd.nwords = nwords;
-  jd.s_elem_bytes = eb;
-  jd.wscale = wscale_of(SBOX_SPECTRUM_B_MAJOR);
-  {
-    // queue counters (and summary[0] = 2^(n-1) again; jd.spec is null: no row written)
-    const JobDesc* nulljobs = nullptr;
-    int one = 1, nq = 64, lay = 0;
-    void* args[] = {(void*)&nulljobs, &jd, &one, &queue, &nq, &lay};
-    s = launch((const void*)&k_init_jobs, dim3(1), dim3(256), args, st);
-    if (s) return s;
-  }
-  const int p = default_split(n);
-  KFn fn = lookup_kernel(n, p, kStoreB);
-  if (!fn) return fail(SBOX_ERR_INVALID_ARG, "no kernel for n=%d", n);
-  int occ = 1;
-  s = occupancy((const void*)fn, &occ);
-  if (s) return s;
-  const int groups = kWG >> (n - p);
-  const long long rows = slab_rows(n, m);
-  const int grid_cap = occ * cus;
-  int chunk = 1;
-  pick_chunk(rows, groups, grid_cap, 0, &chunk);
-  const long long per_item = (long long)groups * chunk;
-  const long long M = 1LL << m;
-  CritLarge cl{};
-  {
-    char* p = reinterpret_cast<char*>(slab) + slab_bytes(n, m);
-    const size_t arr = align256((size_t)4 << m);
-    cl.w0 = reinterpret_cast<int32_t*>(p);
-    cl.mw = reinterpret_cast<int32_t*>(p + arr);
-    cl.ac = reinterpret_cast<int32_t*>(p + 2 * arr);
-    cl.pw = reinterpret_cast<int32_t*>(p + 3 * arr);
-    long long M_ = M;
-    int n_ = n;
-    void* af[] = {&M_, &n_, &cl};
-    s = launch((const void*)&k_crit_fill, dim3((unsigned)std::min<long long>(1024, (M + 255) / 256)), dim3(256), af,
-               st);
-    if (s) return s;
-  }
-  int qi = 1;
-  for (long long b0 = 0; b0 < M; b0 += rows, ++qi) {
-    if (qi >= 64) {
-      int* q = queue + 1;
-      long long cnt = 63;
-      void* za[] = {&q, &cnt};
-      s = launch((const void*)&k_zero, dim3(1), dim3(256), za, st);
-      if (s) return s;
-      qi = 1;
-    }
-    // rows b0 .. b0 + rows - 1 of W into the slab (Gray block inverse_gray(b0 / rows), as for a-major)
-    KParams kp{};
-    kp.job0 = jd;
-    kp.job0.spec = slab;
-    kp.njobs = 1;
-    kp.chunk = chunk;
-    kp.queue = queue + qi;
-    kp.kbase = inverse_gray(b0 / rows) * rows;
-    kp.kcount = rows;
-    kp.row0 = b0;
-    kp.rows = rows;
-    kp.total_items = (rows + per_item - 1) / per_item;
-    const int grid = (int)std::min<long long>(grid_cap, kp.total_items);
-    void* args[] = {&kp};
-    s = launch((const void*)fn, dim3(grid), dim3(kWG), args, st);
-    if (s) return s;
-    const unsigned nrows = (unsigned)std::min(rows, M - b0);
-    {
-      int32_t* sl = slab;
-      int n_ = n;
-      long long b0_ = b0, M_ = M;
-      void* a2[] = {&sl, &n_, &b0_, &M_, &cl};
-      s = launch((const void*)&k_crit_pass_a, dim3(nrows << (n - 12)), dim3(256), a2, st);
-      if (s) return s;
-    }
-    {
-      const int32_t* sl = slab;
-      int n_ = n;
-      long long b0_ = b0, M_ = M;
-      void* a4[] = {(void*)&sl, &n_, &b0_, &M_, &cl};
-      s = launch((const void*)&k_crit_pass_b, dim3(nrows * 64), dim3(256), a4, st);
-      if (s) return s;
-    }
-  }
-  long long M_ = M;
-  void* ar[] = {&M_, &cl, &summary, &w0, &minwt, &acmax, &pcwt};
-  return launch((const void*)&k_crit_reduce, dim3((unsigned)std::min<long long>(256, (M + 255) / 256)), dim3(256), ar,
-                st);
-}
 }  // namespace
 
 sbox_status sbox_criteria_ex(const void* S, int n, int m, int s_elem_bytes, int32_t* summary, int32_t* w0_per_b,
@@ -1162,14 +1049,9 @@ sbox_status sbox_criteria_ex(const void* S, int n, int m, int s_elem_bytes, int3
     if (s) return s;
   }
   if (use_ws) {
-    if (n <= 15)  // finishes the summary itself
-      return criteria_reg(S, n, m, s_elem_bytes, summary, w0_per_b, minwt_per_b, acmax_per_b, pcwt_per_b,
-                          workspace, st);
-    s = criteria_large(S, n, m, s_elem_bytes, summary, w0_per_b, minwt_per_b, acmax_per_b, pcwt_per_b,
-                       workspace, st);
-    if (s) return s;
-    void* args[] = {&summary};
-    return launch((const void*)&k_criteria_finish, dim3(1), dim3(64), args, st);
+    // finishes the summary itself
+    return criteria_reg(S, n, m, s_elem_bytes, summary, w0_per_b, minwt_per_b, acmax_per_b, pcwt_per_b,
+                        workspace, st);
   }
   const void* fn = s_elem_bytes == 1 ? (const void*)&k_criteria<1>
                  : s_elem_bytes == 2 ? (const void*)&k_criteria<2> : (const void*)&k_criteria<4>;

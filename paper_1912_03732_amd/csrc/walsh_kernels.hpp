@@ -1428,19 +1428,19 @@ __device__ __forceinline__ void group_sync() {
   }
 }
 
-// Reduction over the GL lanes of a group; GL > 64 spans GL / 64 waves that
-// meet in `xr` (one int per wave).
+// Reduction over the GL lanes of a group; GL > 64 spans GL / 64 <= 16 waves
+// that meet in `xr` (one int per wave).
 template <int GL, bool IS_MAX>
 __device__ __forceinline__ int crit_group_reduce(int v, int* xr, int l) {
   if constexpr (GL <= 64) {
     return group_reduce<GL, IS_MAX>(v);
   } else {
+    constexpr int NW = GL / 64;  // waves of the group, <= 16
     v = group_reduce<64, IS_MAX>(v);
     if ((l & 63) == 0) xr[l >> 6] = v;
     __syncthreads();
-    int r = xr[0];
-#pragma unroll
-    for (int w = 1; w < GL / 64; ++w) r = IS_MAX ? max(r, xr[w]) : min(r, xr[w]);
+    // one wave value per lane, then a reduction inside each row of 16 lanes
+    const int r = group_reduce<NW, IS_MAX>(xr[l & (NW - 1)]);
     __syncthreads();
     return r;
   }
@@ -1555,6 +1555,11 @@ __global__ __launch_bounds__(crit_reg_wg(N)) void k_crit_reg(const CritRegParams
       ci[__builtin_popcount(j)] |= (uint32_t)s;
       v[j] = s;
     }
+    // group results of the first transform now (a convergent reduction the
+    // compiler cannot sink past the second transform with all the squares)
+    int mw = first_class<RB>(ci, l == 0) + lw;
+    mxsq = crit_group_reduce<GL, true>(mxsq, xr[grp], l);
+    mw = crit_group_reduce<GL, false>(mw, xr[grp], l);
     // ---- second transform: all register bits of B / C
     reg_stages<R, 0, RB>(v);
     if constexpr (THREE) {
@@ -1589,11 +1594,8 @@ __global__ __launch_bounds__(crit_reg_wg(N)) void k_crit_reg(const CritRegParams
       pc[__builtin_popcount(j)] |= (uint32_t)v[j];
     }
     // ---- per-lane results, then the group's
-    int mw = first_class<RB>(ci, l == 0) + lw;
     int pw = first_class<RB>(pc, l == 0) + lw;
     int ac = max(vmax, -vmin) >> (N - 2);  // |V| = 2^(n-2) |r|, exact
-    mxsq = crit_group_reduce<GL, true>(mxsq, xr[grp], l);
-    mw = crit_group_reduce<GL, false>(mw, xr[grp], l);
     ac = crit_group_reduce<GL, true>(ac, xr[grp], l);
     pw = crit_group_reduce<GL, false>(pw, xr[grp], l);
     if (mw > N) mw = N + 1;
@@ -1639,6 +1641,185 @@ __global__ __launch_bounds__(crit_reg_wg(N)) void k_crit_reg(const CritRegParams
   }
 }
 
+// ---------------------------------------------------------------------------
+// Component criteria at n = 16, register-blocked: one workgroup of 1024 lanes
+// (16 waves) per mask, 64 int32 values per lane (the whole 2^16 entries live
+// in registers), layouts as in k_crit_reg:
+//   A: lane l holds entry (l << 6) | j                      bits 0..5
+//   M: lane (w, i) = (l >> 6, l & 63) holds (w << 12) | (j << 6) | i   bits 6..11
+//   C: lane l holds (P(j) << 10) | l                        bits 10..15
+// with P putting register bit 0 on entry bit 10, bits 1..4 on 12..15 and
+// bit 5 on 11.  A <-> M stays inside each wave (its 2^12 entries): the 16
+// waves take two turns over eight padded 17 KiB blocks, and the waves of the
+// first turn run their stages while the second turn exchanges.  M <-> C
+// crosses waves and runs in two rounds of 2^15 entries (128 KiB), split on
+// entry bit 11, which is register bit 5 in both M and C, so each round
+// empties and refills the same 32 registers.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int crit16_p(int j) { return (j & 1) | (((j >> 5) & 1) << 1) | (((j >> 1) & 15) << 2); }
+
+__global__ __launch_bounds__(1024) void k_crit_reg16(const CritRegParams p) {
+  constexpr int N = 16, R = 64, ROW = 68;
+  __shared__ __attribute__((aligned(16))) int32_t lds[8 * 64 * ROW];  // 136 KiB
+  __shared__ int xr[16];
+  const int l = threadIdx.x;
+  const int w = __builtin_amdgcn_readfirstlane(l >> 6), i = l & 63;  // wave index: uniform, scalar branches
+  const bool first_turn = w < 8;
+  int32_t* blk = lds + (w & 7) * 64 * ROW;  // this wave's block for A <-> M
+  const int nwords = 1 << (N - 5);
+  const long long kend = 1LL << p.m;
+  const long long kfirst = 1 + (long long)blockIdx.x * p.chunk;
+  const int lw = __builtin_popcount(l);
+  int g_nl = 1 << (N - 1), g_unb = 0, g_mw = N + 1, g_ac = 0, g_pw = N + 1;
+
+  uint32_t G[2], Fn[2] = {0, 0};
+  G[0] = G[1] = 0;
+  if (kfirst < kend) {
+    const long long gk = gray(kfirst);
+    for (int b = 0; b < p.m; ++b)
+      if ((gk >> b) & 1) {
+        G[0] ^= p.F[(long long)b * nwords + 2 * l];
+        G[1] ^= p.F[(long long)b * nwords + 2 * l + 1];
+      }
+  }
+  // A rows / M words of this wave's block
+  auto put_a = [&](const int32_t* v) { put_rows<R, ROW>(blk, i, v); };
+  auto get_a = [&](int32_t* v) { get_rows<R, ROW>(blk, i, v); };
+  auto put_m = [&](const int32_t* v) {
+#pragma unroll
+    for (int j = 0; j < R; ++j) blk[j * ROW + i] = v[j];
+  };
+  auto get_m = [&](int32_t* v) {
+#pragma unroll
+    for (int j = 0; j < R; ++j) v[j] = blk[j * ROW + i];
+  };
+  auto wsync = []() {
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  };
+  // M <-> C round r (entry bit 11 = r): entries without bit 11, 2^15 words
+  auto put_m_round = [&](const int32_t* v, int r) {
+#pragma unroll
+    for (int jj = 0; jj < 32; ++jj) lds[(w << 11) | (jj << 6) | i] = v[32 * r + jj];
+  };
+  auto get_m_round = [&](int32_t* v, int r) {
+#pragma unroll
+    for (int jj = 0; jj < 32; ++jj) v[32 * r + jj] = lds[(w << 11) | (jj << 6) | i];
+  };
+  auto put_c_round = [&](const int32_t* v, int r) {
+#pragma unroll
+    for (int jj = 0; jj < 32; ++jj) lds[(((jj >> 1) & 15) << 11) | ((jj & 1) << 10) | l] = v[32 * r + jj];
+  };
+  auto get_c_round = [&](int32_t* v, int r) {
+#pragma unroll
+    for (int jj = 0; jj < 32; ++jj) v[32 * r + jj] = lds[(((jj >> 1) & 15) << 11) | ((jj & 1) << 10) | l];
+  };
+
+  for (long long step = 0; step < p.chunk; ++step) {
+    const long long k = kfirst + step;
+    const bool valid = k < kend;
+    if (step > 0) {
+      G[0] ^= Fn[0];
+      G[1] ^= Fn[1];
+    }
+    if (k + 1 < kend && step + 1 < p.chunk) {
+      const int b = __builtin_ctzll((unsigned long long)(k + 1));
+      Fn[0] = p.F[(long long)b * nwords + 2 * l];
+      Fn[1] = p.F[(long long)b * nwords + 2 * l + 1];
+    }
+    int32_t v[R];
+    // ---- first transform: layout A, popcounts (bits 0..4) and bit 5
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int a = 0; a < 32; ++a) v[t * 32 + a] = (int32_t)__builtin_popcount(G[t] ^ walsh_mask(a)) - 16;
+    reg_stages<R, 5, 6>(v);
+    __syncthreads();  // the previous mask's last reads of the blocks are done
+    if (first_turn) { put_a(v); wsync(); get_m(v); }
+    __syncthreads();
+    if (!first_turn) { put_a(v); wsync(); get_m(v); }
+    reg_stages<R, 0, 6>(v);  // M: bits 6..11
+    __syncthreads();
+    put_m_round(v, 0);
+    __syncthreads();
+    get_c_round(v, 0);
+    __syncthreads();
+    put_m_round(v, 1);
+    __syncthreads();
+    get_c_round(v, 1);
+    reg_stages<R, 1, 5>(v);  // C: bits 12..15
+    // u = -W/2 at a = (P(j) << 10) | l
+    const int w0 = -2 * v[0];  // lane 0
+    uint32_t ci[7] = {0, 0, 0, 0, 0, 0, 0};
+    int mxsq = 0;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const int32_t s = __mul24(v[j], v[j]);
+      mxsq = max(mxsq, s);
+      ci[__builtin_popcount(j)] |= (uint32_t)s;
+      v[j] = s;
+    }
+    // group results of the first transform now (a convergent reduction the
+    // compiler cannot sink past the second transform with all the squares)
+    int mw = first_class<6>(ci, l == 0) + lw;
+    mxsq = crit_group_reduce<1024, true>(mxsq, xr, l);
+    mw = crit_group_reduce<1024, false>(mw, xr, l);
+    // ---- second transform: C bits 10..15, M bits 6..9, A bits 0..5
+    reg_stages<R, 0, 6>(v);
+    __syncthreads();
+    put_c_round(v, 0);
+    __syncthreads();
+    get_m_round(v, 0);
+    __syncthreads();
+    put_c_round(v, 1);
+    __syncthreads();
+    get_m_round(v, 1);
+    reg_stages<R, 0, 4>(v);
+    __syncthreads();
+    if (first_turn) { put_m(v); wsync(); get_a(v); }
+    __syncthreads();
+    if (!first_turn) { put_m(v); wsync(); get_a(v); }
+    reg_stages<R, 0, 6>(v);
+    // V(d) at d = (l << 6) | j
+    if (l == 0) v[0] = 0;
+    uint32_t pc[7] = {0, 0, 0, 0, 0, 0, 0};
+    int vmax = 0, vmin = 0;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      vmax = max(vmax, v[j]);
+      vmin = min(vmin, v[j]);
+      pc[__builtin_popcount(j)] |= (uint32_t)v[j];
+    }
+    int pw = first_class<6>(pc, l == 0) + lw;
+    int ac = max(vmax, -vmin) >> (N - 2);
+    ac = crit_group_reduce<1024, true>(ac, xr, l);
+    pw = crit_group_reduce<1024, false>(pw, xr, l);
+    if (mw > N) mw = N + 1;
+    if (pw > N) pw = N + 1;
+    if (l == 0 && valid) {
+      const long long b = gray(k);
+      const int umax = (int)rintf(sqrtf((float)mxsq));  // mxsq is a perfect square <= 2^30
+      if (p.w0) p.w0[b] = w0;
+      if (p.minwt) p.minwt[b] = mw;
+      if (p.acmax) p.acmax[b] = ac;
+      if (p.pcwt) p.pcwt[b] = pw;
+      g_nl = min(g_nl, (1 << (N - 1)) - umax);
+      g_unb += w0 != 0;
+      g_mw = min(g_mw, mw);
+      g_ac = max(g_ac, ac);
+      g_pw = min(g_pw, pw);
+    }
+  }
+  if (l == 0) {
+    int32_t* o = p.part + 8 * blockIdx.x;
+    o[0] = g_nl;
+    o[1] = g_unb;
+    o[2] = g_mw;
+    o[3] = g_ac;
+    o[4] = g_pw;
+  }
+}
+
 // Aggregates of the register-blocked criteria kernel: the per-workgroup slots
 // folded into crit[] (which holds the start values), then the orders as in
 // k_criteria_finish.
@@ -1665,152 +1846,6 @@ __global__ __launch_bounds__(256) void k_crit_reg_finish(const int32_t* part, in
     crit[3] = crit[1] == 0 ? crit[2] : -1;
     crit[4] = max(crit[4], ac);
     crit[5] = min(crit[5], pw) - 1;
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Criteria of large boxes (n = 15, 16): the spectrum rows of a block of masks
-// are first written into a slab (b-major, W as int32, by the store-mode
-// transform); pass A takes W(0, b) and the smallest nonzero weight, squares
-// W/2 and runs the first 12 stages of the second transform; pass B runs the
-// rest and reduces the autocorrelation V(d) = 2^(n-2) r(d) without writing
-// it back.  Parseval bounds every partial sum of the second transform by
-// sum_a (W/2)^2 = 4^(n-1) < 2^31: int32 is exact.
-// ---------------------------------------------------------------------------
-// Per-mask values of the large path live in workspace arrays (w0, smallest
-// weight of a nonzero W, largest |r|, smallest weight of a nonzero r), so
-// that the many workgroups of one mask meet at that mask's slot and the
-// aggregates are formed once at the end (k_crit_reduce), not by atomics on
-// one address.
-struct CritLarge {
-  int32_t* w0;
-  int32_t* mw;
-  int32_t* ac;
-  int32_t* pw;
-};
-
-// Pass A, one workgroup per 4096-entry segment of a row (mask b = b0 + row):
-// W(0, b) and the smallest weight of a nonzero W in the segment, then
-// (W/2)^2 and the first 12 stages of the second transform, in LDS.
-__global__ __launch_bounds__(256) void k_crit_pass_a(int32_t* slab, int n, long long b0, long long M, CritLarge cl) {
-  __shared__ int32_t t[4096];
-  __shared__ int red[4];
-  const int segs_log = n - 12;
-  const long long row = blockIdx.x >> segs_log;
-  const int seg = blockIdx.x & ((1 << segs_log) - 1);
-  const long long b = b0 + row;
-  if (b == 0 || b >= M) return;  // block-uniform
-  int32_t* base = slab + (row << n) + ((long long)seg << 12);
-  int mw = n + 1;
-  for (int e = threadIdx.x; e < 4096; e += blockDim.x) {
-    const int v = base[e];
-    const int a = (seg << 12) | e;
-    if (a == 0) cl.w0[b] = v;
-    else if (v != 0) mw = min(mw, __builtin_popcount(a));
-    const int hv = v / 2;  // every W is even
-    t[e] = hv * hv;
-  }
-  mw = block_reduce<false>(mw, red);  // its barrier also orders the LDS writes
-  if (threadIdx.x == 0 && mw <= n) atomicMin(&cl.mw[b], mw);
-  for (int sb = 0; sb < 12; ++sb) {
-    for (int e = threadIdx.x; e < 2048; e += blockDim.x) {
-      const int i0 = ((e >> sb) << (sb + 1)) | (e & ((1 << sb) - 1)), i1 = i0 | (1 << sb);
-      const int32_t u = t[i0], v = t[i1];
-      t[i0] = u + v;
-      t[i1] = u - v;
-    }
-    __syncthreads();
-  }
-  for (int e = threadIdx.x; e < 4096; e += blockDim.x) base[e] = t[e];
-}
-
-// Pass B: the remaining n - 12 stages over tiles of 2^(n-12) rows (stride
-// 4096) by 64 columns, then V(d) = 2^(n-2) r(d) reduced in place: the largest
-// |r(d)| and the smallest weight of a nonzero r(d) over d != 0.
-__global__ __launch_bounds__(256) void k_crit_pass_b(const int32_t* slab, int n, long long b0, long long M,
-                                                     CritLarge cl) {
-  __shared__ int32_t t[16 * 64];
-  __shared__ int red[4];
-  const int R = n - 12;
-  const long long row = blockIdx.x >> 6;
-  const int colb = blockIdx.x & 63;
-  const long long b = b0 + row;
-  if (b == 0 || b >= M) return;
-  const int32_t* base = slab + (row << n) + colb * 64;
-  const int TILE = 64 << R;
-  for (int e = threadIdx.x; e < TILE; e += blockDim.x) t[e] = base[((long long)(e >> 6) << 12) | (e & 63)];
-  __syncthreads();
-  for (int sb = 0; sb < R; ++sb) {
-    for (int e = threadIdx.x; e < TILE / 2; e += blockDim.x) {
-      const int col = e & 63, rr = e >> 6;
-      const int r0 = ((rr >> sb) << (sb + 1)) | (rr & ((1 << sb) - 1));
-      const int i0 = (r0 << 6) | col, i1 = ((r0 | (1 << sb)) << 6) | col;
-      const int32_t u = t[i0], v = t[i1];
-      t[i0] = u + v;
-      t[i1] = u - v;
-    }
-    __syncthreads();
-  }
-  int ac = 0, pw = n + 1;
-  for (int e = threadIdx.x; e < TILE; e += blockDim.x) {
-    const int d = ((e >> 6) << 12) | (colb * 64) | (e & 63);
-    if (d == 0) continue;
-    const int r = t[e] >> (n - 2);  // exact
-    ac = max(ac, r < 0 ? -r : r);
-    if (r != 0) pw = min(pw, __builtin_popcount(d));
-  }
-  ac = block_reduce<true>(ac, red);
-  pw = block_reduce<false>(pw, red);
-  if (threadIdx.x == 0) {
-    if (ac > 0) atomicMax(&cl.ac[b], ac);
-    if (pw <= n) atomicMin(&cl.pw[b], pw);
-  }
-}
-
-// Slots start at their identities: 0 for the largest |r|, n + 1 for the
-// smallest weights.
-__global__ __launch_bounds__(256) void k_crit_fill(long long M, int n, CritLarge cl) {
-  for (long long b = blockIdx.x * (long long)blockDim.x + threadIdx.x; b < M; b += (long long)gridDim.x * blockDim.x) {
-    cl.w0[b] = 0;
-    cl.mw[b] = n + 1;
-    cl.ac[b] = 0;
-    cl.pw[b] = n + 1;
-  }
-}
-
-// Aggregates over b = 1 .. M - 1 (unbalanced count, smallest weights,
-// largest |r|) into crit[], and the optional per-mask outputs.
-__global__ __launch_bounds__(256) void k_crit_reduce(long long M, CritLarge cl, int32_t* crit, int32_t* w0,
-                                                     int32_t* minwt, int32_t* acmax, int32_t* pcwt) {
-  __shared__ int red[4];
-  int unb = 0, mw = 0x7fffffff, ac = 0, pw = 0x7fffffff;
-  for (long long b = 1 + blockIdx.x * (long long)blockDim.x + threadIdx.x; b < M;
-       b += (long long)gridDim.x * blockDim.x) {
-    const int v0 = cl.w0[b], m0 = cl.mw[b], a0 = cl.ac[b], p0 = cl.pw[b];
-    unb += v0 != 0;
-    mw = min(mw, m0);
-    ac = max(ac, a0);
-    pw = min(pw, p0);
-    if (w0) w0[b] = v0;
-    if (minwt) minwt[b] = m0;
-    if (acmax) acmax[b] = a0;
-    if (pcwt) pcwt[b] = p0;
-  }
-  // block sums and extremes, then one atomic each per workgroup
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) unb += __shfl_xor(unb, o, 64);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = unb;
-  __syncthreads();
-  unb = red[0] + red[1] + red[2] + red[3];
-  __syncthreads();
-  mw = block_reduce<false>(mw, red);
-  ac = block_reduce<true>(ac, red);
-  pw = block_reduce<false>(pw, red);
-  if (threadIdx.x == 0) {
-    if (unb) atomicAdd(&crit[1], unb);
-    atomicMin(&crit[2], mw);
-    atomicMax(&crit[4], ac);
-    atomicMin(&crit[5], pw);
   }
 }
 
