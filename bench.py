@@ -56,6 +56,9 @@ def parse():
                     help="butterfly engine for the 16x16 kernel: 0 library default, 1 VALU, 2 matrix cores")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters) and exit")
+    ap.add_argument("--extra-only", default="",
+                    help="comma-separated name prefixes: time only those extra workloads (e.g. criteria_16x16, "
+                         "for a profiler run), print them as one JSON object and exit")
     args = ap.parse_args()
     if not args.quick:
         args.batched = args.extra = True
@@ -167,6 +170,12 @@ def main():
     if args.copy_calibration:
         copy_calibration(torch)
         return
+    if args.extra_only:
+        dev = torch.device("cuda:0")
+        torch.cuda.set_device(dev)
+        only = tuple(p for p in args.extra_only.split(",") if p)
+        print(json.dumps({"extra": bench_extra(torch, B, inputs, dev, only)}), flush=True)
+        return
     n = m = 16
     w = inputs.workload_16x16()
     S_host = w["perm"]
@@ -274,9 +283,13 @@ def _time_call(torch, fn, reps):
     return a.elapsed_time(b) / reps
 
 
-def bench_extra(torch, B, inputs, dev):
-    """The other workloads, timed with HIP events (ms per call)."""
+def bench_extra(torch, B, inputs, dev, only=()):
+    """The other workloads, timed with HIP events (ms per call); `only`
+    (name prefixes) restricts them."""
     out = {}
+
+    def want(name):
+        return not only or any(name.startswith(p) for p in only)
 
     def single(S_host, n, m, layout=0, reps=5):
         S = B.table_to_device(S_host, m, device=dev)
@@ -309,20 +322,26 @@ def bench_extra(torch, B, inputs, dev):
         return row
 
     w8 = inputs.workload_8x8()
-    out["8x8_perm_fused"] = single(w8["perm"], 8, 8, reps=50)
-    out["8x8_perm_spectrum_b"] = single(w8["perm"], 8, 8, 1, reps=50)
-    out["8x8_perm_spectrum_a"] = single(w8["perm"], 8, 8, 2, reps=50)
-    out["12x12_perm_fused"] = single(inputs.permutation(12, inputs.rng(inputs.SEED_BASE + 6)), 12, 12, reps=50)
     ns = inputs.workload_nonsquare()
-    out["16x20_fused"] = single(ns["s16x20"], 16, 20, reps=2)
-    out["20x16_fused"] = single(ns["s20x16"], 20, 16, reps=1)
-    out["12x12_slice_spectrum_a"] = single(ns["slice12"], 12, 12, 2, reps=10)
-    out["12x12_slice_spectrum_b"] = single(ns["slice12"], 12, 12, 1, reps=10)
-    out["16x16_perm_spectrum_b"] = single(inputs.workload_16x16()["perm"], 16, 16, 1, reps=2)
-    out["16x16_perm_spectrum_a"] = single(inputs.workload_16x16()["perm"], 16, 16, 2, reps=2)
+    singles = [("8x8_perm_fused", lambda: single(w8["perm"], 8, 8, reps=50)),
+               ("8x8_perm_spectrum_b", lambda: single(w8["perm"], 8, 8, 1, reps=50)),
+               ("8x8_perm_spectrum_a", lambda: single(w8["perm"], 8, 8, 2, reps=50)),
+               ("12x12_perm_fused", lambda: single(inputs.permutation(12, inputs.rng(inputs.SEED_BASE + 6)), 12, 12,
+                                                   reps=50)),
+               ("16x20_fused", lambda: single(ns["s16x20"], 16, 20, reps=2)),
+               ("20x16_fused", lambda: single(ns["s20x16"], 20, 16, reps=1)),
+               ("12x12_slice_spectrum_a", lambda: single(ns["slice12"], 12, 12, 2, reps=10)),
+               ("12x12_slice_spectrum_b", lambda: single(ns["slice12"], 12, 12, 1, reps=10)),
+               ("16x16_perm_spectrum_b", lambda: single(inputs.workload_16x16()["perm"], 16, 16, 1, reps=2)),
+               ("16x16_perm_spectrum_a", lambda: single(inputs.workload_16x16()["perm"], 16, 16, 2, reps=2))]
+    for name, run in singles:
+        if want(name):
+            out[name] = run()
     # component criteria (balancedness, correlation immunity, autocorrelation): two
     # int32 transforms per mask, register-blocked
     for n in (8, 12, 14, 16):
+        if not want("criteria_%dx%d" % (n, n)):
+            continue
         S = B.table_to_device(inputs.permutation(n, inputs.rng(inputs.SEED_BASE + 6)), n, device=dev)
         summ = torch.empty(8, dtype=torch.int32, device=dev)
         sptr = int(torch.cuda.current_stream(dev).cuda_stream)
@@ -344,6 +363,8 @@ def bench_extra(torch, B, inputs, dev):
                                                        "unit": "TOP/s", "frac": tops / PEAK_INT32_TOPS}}
     # |W| histogram over all nonzero masks (fused into the transform)
     for name, S_host, n in (("8x8_perm", w8["perm"], 8), ("16x16_perm", inputs.workload_16x16()["perm"], 16)):
+        if not want("histogram_" + name):
+            continue
         S = B.table_to_device(S_host, n, device=dev)
         hist = torch.empty((1 << (n - 1)) + 1, dtype=torch.int64, device=dev)
         nl = torch.empty(1, dtype=torch.int32, device=dev)
@@ -366,6 +387,8 @@ def bench_extra(torch, B, inputs, dev):
                                                    "unit": "TOP/s", "frac": tops / PEAK_PK16_TOPS}}
     # unit-difference autocorrelations (strict avalanche / bit independence)
     for name, S_host, n in (("8x8_perm", w8["perm"], 8), ("16x16_perm", inputs.workload_16x16()["perm"], 16)):
+        if not want("avalanche_" + name):
+            continue
         S = B.table_to_device(S_host, n, device=dev)
         r = torch.empty(n << n, dtype=torch.int32, device=dev)
         summ = torch.empty(3, dtype=torch.int32, device=dev)
