@@ -56,6 +56,8 @@ def parse():
                     help="butterfly engine for the 16x16 kernel: 0 library default, 1 VALU, 2 matrix cores")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters) and exit")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="time only the 4096-box batch (for a profiler run), print it as one JSON object and exit")
     ap.add_argument("--extra-only", default="",
                     help="comma-separated name prefixes: time only those extra workloads (e.g. criteria_16x16, "
                          "for a profiler run), print them as one JSON object and exit")
@@ -169,6 +171,11 @@ def main():
 
     if args.copy_calibration:
         copy_calibration(torch)
+        return
+    if args.batched_only:
+        dev = torch.device("cuda:0")
+        torch.cuda.set_device(dev)
+        print(json.dumps({"batched": bench_batched(torch, B, inputs, dev)}), flush=True)
         return
     if args.extra_only:
         dev = torch.device("cuda:0")

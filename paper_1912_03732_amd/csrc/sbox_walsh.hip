@@ -680,12 +680,17 @@ sbox_status launch_batch(const BatchLayout& L, void* ws, hipStream_t st) {
   int* queue = reinterpret_cast<int*>(ws);
   const JobDesc* dtab = reinterpret_cast<const JobDesc*>(reinterpret_cast<char*>(ws) + kQueueBytes);
   sbox_status s;
-  // bit-slice every table (grid.y <= 65535 jobs per launch)
+  // bit-slice every table (grid.y <= 65535 jobs per launch): waves of 64
+  // threads striding over a job's words, one per 256 words of the largest
+  // job (one up to n = 13); idle workgroups would only cost dispatch time
+  int maxw = 1;
+  for (const JobDesc& jd : L.descs) maxw = std::max(maxw, jd.nwords);
+  const unsigned gx = (unsigned)std::min(32, (maxw + 255) / 256);
   for (int j0 = 0; j0 < L.count; j0 += 65535) {
     const int nj = std::min(65535, L.count - j0);
     const JobDesc* d = dtab + j0;
     void* args[] = {(void*)&d};
-    s = launch((const void*)&k_bitslice_jobs, dim3(8, nj), dim3(256), args, st);
+    s = launch((const void*)&k_bitslice_jobs, dim3(gx, nj), dim3(64), args, st);
     if (s) return s;
   }
   // per-job init (NL start value, maxabs[0], b = 0 spectrum row), then the queue counters

@@ -826,8 +826,10 @@ __global__ __launch_bounds__(kWG, ROUNDS) void k_walsh_mfma16(const KParams kp) 
 //   1. Popcount stages as fp16 bit patterns (1536 + c', as in the n = 16
 //      kernel), the x5 pair packed into one register.
 //   2. A wave-private LDS transpose: lane (x8, x9, a'3, a'4, x10, x11)
-//      receives register (x6, x7, a'0, a'1, a'2) (the XOR swizzle of the
-//      address keeps both sides free of bank conflicts).
+//      receives register (x6, x7, a'0, a'1, a'2).  Rows of 68 words (one
+//      per receiving register) keep both sides free of bank conflicts: a
+//      write lands on bank 4 x6x7 + (receiving lane) mod 64, and the four
+//      registers of an MFMA operand are read as pairs straight into place.
 //   3. Pass 1, for each (a'0, a'1, a'2): the registers over (x6, x7) with
 //      their x5 halves are the A operand of v_mfma_f32_16x16x32_f16 with rows
 //      (x8, x9, a'3, a'4) = lane bits 0..3 and K slots (x5, x6, x7, x10, x11),
@@ -844,14 +846,14 @@ typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
 __global__ __launch_bounds__(kWG, 4) void k_walsh_mfma12(const KParams kp) {
   constexpr int NW = 2;
   constexpr int GPW = kWG / 64;               // masks (waves) per workgroup
-  __shared__ uint32_t lds[GPW * 32 * 64];     // 8 KiB per wave
+  __shared__ uint32_t lds[GPW * 32 * 68];     // 8.5 KiB per wave: 32 rows of 68 words
   __shared__ long long s_item;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int C = kp.chunk;
-  uint32_t* wl = lds + wave * (32 * 64);
+  uint32_t* wl = lds + wave * (32 * 68);
 
   f16x8 hb0, hb1;
   f16x4 hc;
@@ -926,25 +928,30 @@ __global__ __launch_bounds__(kWG, 4) void k_walsh_mfma12(const KParams kp) {
         const uint32_t c1 = __builtin_popcount(G[1] ^ walsh_mask(a)) + (0x6600 - 16);
         const int dreg = xs + 4 * (a & 7);
         const int dlane = dl0 | ((a >> 3) << 2);
-        wl[dreg * 64 + (dlane ^ (xs << 2))] = __builtin_amdgcn_perm(c1, c0, 0x05040100u);
+        wl[dreg * 68 + dlane] = __builtin_amdgcn_perm(c1, c0, 0x05040100u);
       }
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
       __builtin_amdgcn_wave_barrier();
       uint32_t R[32];
 #pragma unroll
-      for (int d = 0; d < 32; ++d) R[d] = wl[d * 64 + (lane ^ ((d & 3) << 2))];
-      // ---- 3-4. the two passes and the maximum
+      for (int d = 0; d < 32; ++d) R[d] = wl[d * 68 + lane];
+      // ---- 3-4. the two passes and the maximum: all first-pass products
+      // first, so the casts of one wait on products issued long before
       float m0 = 0.0f, m1 = 0.0f;
+      f32x4 d0[8], d1[8];
 #pragma unroll
       for (int t = 0; t < 8; ++t) {
         const f16x8 av = as_f16x8(R[4 * t], R[4 * t + 1], R[4 * t + 2], R[4 * t + 3]);
-        const f32x4 d0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(av, hb0, cfix, 0, 0, 0);
-        const f32x4 d1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(av, hb1, zero, 0, 0, 0);
+        d0[t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(av, hb0, cfix, 0, 0, 0);
+        d1[t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(av, hb1, zero, 0, 0, 0);
+      }
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
         f16x4 a0, a1;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          a0[i] = (_Float16)d0[i];
-          a1[i] = (_Float16)d1[i];
+          a0[i] = (_Float16)d0[t][i];
+          a1[i] = (_Float16)d1[t][i];
         }
         const f32x4 e0 = __builtin_amdgcn_mfma_f32_16x16x16f16(a0, hc, zero, 0, 0, 0);
         const f32x4 e1 = __builtin_amdgcn_mfma_f32_16x16x16f16(a1, hc, zero, 0, 0, 0);
@@ -1206,7 +1213,7 @@ __global__ __launch_bounds__(256) void k_bitslice_big(const void* S, int L, int 
 }
 
 // Batched: blockIdx.y selects the job, threads stride over its words.
-__global__ __launch_bounds__(256) void k_bitslice_jobs(const JobDesc* jobs) {
+__global__ __launch_bounds__(64) void k_bitslice_jobs(const JobDesc* jobs) {
   const JobDesc jd = jobs[blockIdx.y];
   for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < jd.nwords; w += gridDim.x * blockDim.x) {
     uint32_t* F = const_cast<uint32_t*>(jd.F);
