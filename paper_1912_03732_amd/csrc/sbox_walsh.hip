@@ -57,6 +57,7 @@ KFn pick_mode(int mode, bool any_p) {
   if constexpr (P == default_split(N)) {  // the other modes exist for the default split only
     if (any_p) return nullptr;
     if (mode == kStoreB) return &k_walsh<N, P, kStoreB>;
+    if (mode == kSlab16) return &k_walsh<N, P, kSlab16>;
     if (mode == kStoreA) return &k_walsh<N, P, kStoreA>;
     if (mode == kHist) return &k_walsh<N, P, kHist>;
     if (mode == kHistBig) return &k_walsh<N, P, kHistBig>;
@@ -230,12 +231,13 @@ int mode_of(int layout) { return layout == 1 ? kStoreB : (layout == 2 ? kStoreA 
 // a-major output of a large spectrum (n <= 16, n + m >= 24): rows of a block
 // of masks go through a b-major slab that a tiled transpose turns into columns.
 bool use_slab(int n, int m, int layout) { return layout == 2 && n <= 16 && n >= 6 && n + m >= 24; }
-// slab of 2^SBW_SLAB_LOG int32 (256 MiB by default)
+// slab of 2^SBW_SLAB_LOG int16 entries (256 MiB by default: measured best for
+// 16 x 16 a-major among 2^25 .. 2^30; longer runs per spectrum row than 2^26)
 #ifndef SBW_SLAB_LOG
-#define SBW_SLAB_LOG 26
+#define SBW_SLAB_LOG 27
 #endif
 long long slab_rows(int n, int m) { return std::min(1LL << m, std::max(64LL, (1LL << SBW_SLAB_LOG) >> n)); }
-size_t slab_bytes(int n, int m) { return align256((size_t)slab_rows(n, m) << n) * 4; }
+size_t slab_bytes(int n, int m) { return align256(((size_t)slab_rows(n, m) << n) * 2); }  // int16 rows
 
 // Chunk and grid for a kernel with `groups` thread groups per workgroup over
 // `masks` masks per job x `njobs` jobs.
@@ -365,7 +367,7 @@ sbox_status run_single(const void* S, int n, int m, int eb, int32_t* maxabs, int
   if (n <= 16 && use_slab(n, m, layout)) {
     // b-major rows of each aligned block of masks into the slab, then transpose
     const int p = default_split(n);
-    KFn fn = lookup_kernel(n, p, kStoreB);
+    KFn fn = lookup_kernel(n, p, kSlab16);
     if (!fn) return fail(SBOX_ERR_INVALID_ARG, "no kernel for n=%d", n);
     int occ = 1;
     s = occupancy((const void*)fn, &occ);
@@ -406,12 +408,13 @@ sbox_status run_single(const void* S, int n, int m, int eb, int32_t* maxabs, int
       void* args[] = {&kp};
       s = launch((const void*)fn, dim3(grid), dim3(kWG), args, st);
       if (s) return s;
-      int n_ = n, m_ = m, B_ = (int)rows;
+      int n_ = n, m_ = m, B_ = (int)rows, wsc = jd.wscale, eb_ = jd.s_elem_bytes;
       long long b0_ = b0;
-      int32_t* slab_ = slab;
-      void* targs[] = {&slab_, &n_, &spec, &m_, &b0_, &B_};
-      s = launch((const void*)&k_transpose_slab, dim3((unsigned)(((1LL << n) + 63) / 64), (unsigned)((rows + 63) / 64)),
-                 dim3(256), targs, st);
+      const int16_t* slab_ = reinterpret_cast<const int16_t*>(slab);
+      const void* S_ = jd.S;
+      void* targs[] = {(void*)&slab_, &n_, &spec, &m_, &b0_, &B_, &wsc, (void*)&S_, &eb_};
+      s = launch((const void*)&k_transpose_slab16,
+                 dim3((unsigned)(((1LL << n) + 127) / 128), (unsigned)((rows + 63) / 64)), dim3(256), targs, st);
       if (s) return s;
     }
     return SBOX_OK;

@@ -49,7 +49,8 @@ namespace sbw {
 
 constexpr int kWG = 256;  // threads per workgroup (4 waves)
 
-enum Mode : int { kMax = 0, kStoreB = 1, kStoreA = 2, kBlock = 3, kHist = 4, kHistBig = 5 };
+// kSlab16: b-major rows of -W/2 as int16 into a slab (the a-major path transposes them)
+enum Mode : int { kMax = 0, kStoreB = 1, kStoreA = 2, kBlock = 3, kHist = 4, kHistBig = 5, kSlab16 = 6 };
 
 // |W| histogram: kHist counts the bins |W|/2 < kHistBins - 1 in LDS per
 // workgroup and only the number of larger values in the last LDS bin (no
@@ -93,6 +94,7 @@ struct KParams {
 
 typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));
 typedef __attribute__((address_space(1))) int32_t gint32;  // global memory
+typedef __attribute__((address_space(1))) int16_t gint16;
 typedef int16_t s16x2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ uint32_t pk_add(uint32_t a, uint32_t b) {
@@ -220,7 +222,7 @@ constexpr int kLdsStride = kWG + 1;  // padded LDS row (odd number of words)
 // kernel with the two-round exchange fits two (<= 256 VGPRs per lane).
 template <int N, int P_, int MODE>
 constexpr int min_blocks() {
-  return (N == 16 && P_ == 8 && (MODE == kMax || MODE == kStoreB || MODE == kHist)) ? 2 : 1;  // kHistBig: 1
+  return (N == 16 && P_ == 8 && (MODE == kMax || MODE == kStoreB || MODE == kSlab16 || MODE == kHist)) ? 2 : 1;  // kHistBig: 1
 }
 
 template <int N, int P_, int MODE>
@@ -237,7 +239,7 @@ __global__ __launch_bounds__(kWG, (min_blocks<N, P_, MODE>())) void k_walsh(cons
   constexpr int U2 = (Q >= 1 && Q <= P - 1) ? (1 << (P - 1 - Q)) : 1;
 
   constexpr bool TWO_ROUND =
-      ((MODE == kMax || MODE == kStoreB || MODE == kHist || MODE == kHistBig) && Q == P && P == 8);
+      ((MODE == kMax || MODE == kStoreB || MODE == kSlab16 || MODE == kHist || MODE == kHistBig) && Q == P && P == 8);
   constexpr int LDS_WORDS = (Q == 0) ? 1 : (Q <= P - 1) ? NR * kWG : (TWO_ROUND ? 64 : NR) * kLdsStride;
   __shared__ uint32_t lds[LDS_WORDS];
   __shared__ int red[kWG / 64];
@@ -324,7 +326,8 @@ __global__ __launch_bounds__(kWG, (min_blocks<N, P_, MODE>())) void k_walsh(cons
       }
       const uint32_t b = (uint32_t)gray(k);
       // a b-major slab holds rows [row0, row0 + rows) only
-      const bool inslab = MODE != kStoreB || kp.rows == 0 || (unsigned long long)((long long)b - kp.row0) < (unsigned long long)kp.rows;
+      const bool inslab = (MODE != kStoreB && MODE != kSlab16) || kp.rows == 0 ||
+                          (unsigned long long)((long long)b - kp.row0) < (unsigned long long)kp.rows;
       const bool valid = inrange && k != 0 && inslab;
       const long long slot = k - kp.kbase;  // kBlock only
 
@@ -334,6 +337,9 @@ __global__ __launch_bounds__(kWG, (min_blocks<N, P_, MODE>())) void k_walsh(cons
       gint32* gdst = nullptr;
       if constexpr (MODE == kStoreB) gdst = (gint32*)(jd.spec + ((size_t)(b - kp.row0) << N));
       if constexpr (MODE == kStoreA) gdst = (gint32*)(jd.spec + b);
+      gint16* hdst = nullptr;  // kSlab16: int16 rows
+      if constexpr (MODE == kSlab16)
+        hdst = (gint16*)(reinterpret_cast<int16_t*>(jd.spec) + ((size_t)(b - kp.row0) << N));
       if constexpr (MODE == kBlock)
         gdst = (gint32*)(kp.blockout + ((size_t)slot << (16 + kp.nblk_log)) + ((size_t)xblk << 16));
       auto emit = [&](uint32_t a, int v) {  // v = -W(a,b)/2 (or the block value)
@@ -347,6 +353,9 @@ __global__ __launch_bounds__(kWG, (min_blocks<N, P_, MODE>())) void k_walsh(cons
         if constexpr (MODE == kStoreB)
           *(gint32*)((__attribute__((address_space(1))) char*)gdst + (uint32_t)(a << 2)) = jd.wscale * v;
         if constexpr (MODE == kStoreA) gdst[(size_t)a << jd.m] = jd.wscale * v;
+        // |v| <= 2^15; v = 2^15 (an affine component at n = 16) wraps to -2^15
+        if constexpr (MODE == kSlab16)
+          *(gint16*)((__attribute__((address_space(1))) char*)hdst + (uint32_t)(a << 1)) = (int16_t)v;
         if constexpr (MODE == kBlock)
           *(gint32*)((__attribute__((address_space(1))) char*)gdst + (uint32_t)(a << 2)) = v;
       };
@@ -1883,30 +1892,40 @@ __global__ void k_criteria_finish(int32_t* crit) {
   }
 }
 // ---------------------------------------------------------------------------
-// a-major spectrum of a large box: the fused kernel writes the rows of an
-// aligned block of masks b in [b0, b0 + B) (b-major, int32) into a slab, and
-// this kernel transposes the slab into columns b0 .. b0 + B - 1 of the
-// a-major matrix through a 64 x 64 LDS tile, so that both the slab reads (along
-// a) and the spectrum writes (along b) are 256-byte runs.  Column b = 0 is
+// a-major spectrum of a large box: the fused kernel (mode kSlab16) writes the
+// rows of an aligned block of masks b in [b0, b0 + B) as int16 -W/2 into a
+// slab, and this kernel transposes the slab into columns b0 .. b0 + B - 1 of
+// the a-major matrix (scaled by wscale: W or W/2) through an LDS tile of 64
+// rows by 128 entries read as int16 pairs, so that the slab reads (along a)
+// and the spectrum writes (along b) are 256-byte runs.  Column b = 0 is
 // written by the init kernel and skipped here.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_transpose_slab(const int32_t* slab, int n, int32_t* spec, int m,
-                                                        long long b0, int B) {
-  __shared__ int32_t tile[64][65];
+__global__ __launch_bounds__(256) void k_transpose_slab16(const int16_t* slab, int n, int32_t* spec, int m,
+                                                          long long b0, int B, int wscale, const void* S, int eb) {
+  __shared__ int32_t tile[64][65];  // tile[j][p]: entries a0 + 2p, a0 + 2p + 1 of row j
   const long long N = 1LL << n;
-  const long long a0 = (long long)blockIdx.x * 64;
+  const long long a0 = (long long)blockIdx.x * 128;
   const int j0 = blockIdx.y * 64;
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   for (int r = ty; r < 64; r += 4) {
     const int j = j0 + r;
-    if (j < B && a0 + tx < N) tile[r][tx] = slab[(long long)j * N + a0 + tx];
+    if (j < B && a0 + 2 * tx < N) tile[r][tx] = reinterpret_cast<const int32_t*>(slab + (long long)j * N + a0)[tx];
   }
   __syncthreads();
-  for (int r = ty; r < 64; r += 4) {
+  const int j = j0 + tx;
+  const long long b = b0 + j;
+  // the one value int16 cannot hold: -W/2 = +2^15, stored as -2^15.  It only
+  // occurs for an affine component at n = 16, W(a, b) = 2^16 (-1)^(b . S(0)).
+  const uint32_t s0 = eb == 1 ? *reinterpret_cast<const uint8_t*>(S)
+                    : eb == 2 ? *reinterpret_cast<const uint16_t*>(S) : *reinterpret_cast<const uint32_t*>(S);
+  const bool flip = __builtin_popcount((uint32_t)b & s0) & 1;
+  for (int r = ty; r < 128; r += 4) {
     const long long a = a0 + r;
-    const int j = j0 + tx;
+    const uint32_t pair = (uint32_t)tile[tx][r >> 1];
+    int v = (int16_t)((r & 1) ? (pair >> 16) : (pair & 0xFFFFu));
+    if (v == -32768 && flip) v = 32768;
     // streaming stores: the final spectrum must not evict the slab from the caches
-    if (j < B && a < N && b0 + j != 0) __builtin_nontemporal_store(tile[tx][r], &spec[(a << m) + b0 + j]);
+    if (j < B && a < N && b != 0) __builtin_nontemporal_store(wscale * v, &spec[(a << m) + b]);
   }
 }
 

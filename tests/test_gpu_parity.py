@@ -224,10 +224,31 @@ def test_a_major_through_transposed_slabs(n, m):
     assert nl == oracle.walsh_nl(S, n, m, nthreads=NT)[0]
 
 
+@pytest.mark.parametrize("kind", ["a", "lat-a"])
+def test_a_major_slab_affine_components_16(kind):
+    """n = 16 through the int16 slab: the low output nibble is x -> (x & 15) ^ 5,
+    so every mask b < 16 is affine with W(b, b) = 2^16 (-1)^(b . 5), both
+    signs, the one value the int16 slab cannot hold (restored from b . S(0));
+    the high nibble is a random permutation's."""
+    n, m = 16, 8
+    x = np.arange(1 << n)
+    S = ((x & 15) ^ 5) | ((inputs.permutation(n, inputs.rng(13020)) & 15) << 4)
+    nl, mx, spec = gpu_nl(S, n, m, spectrum=kind)
+    ref = oracle.spectrum(S, n, m, oracle.A_MAJOR)
+    if kind == "lat-a":
+        ref = ref // 2
+    assert np.array_equal(spec, ref)
+    full = 1 << n if kind == "a" else 1 << (n - 1)
+    for b in range(1, 16):
+        assert spec[b, b] == (-full if bin(b & 5).count("1") & 1 else full)
+    assert nl == 0
+
+
 def test_a_major_many_slabs_sampled_columns():
-    """n = 12, m = 16: four slabs of 2^14 masks; every slab's columns land in
-    place (sampled masks from each slab against the oracle)."""
-    n, m = 12, 16
+    """n = 13, m = 16: four slabs of 2^14 masks (2^27-entry slabs); every
+    slab's columns land in place (sampled masks from each slab against the
+    oracle)."""
+    n, m = 13, 16
     S = table(n, m, 13050)
     t = dev_table(S, m)
     nl, mx, spec = B.walsh_nl(t, n, m, spectrum="a")
