@@ -995,8 +995,8 @@ sbox_status criteria_reg(const void* S, int n, int m, int eb, int32_t* summary, 
   static const void* const fns[] = {
       (const void*)&k_crit_reg<5>,  (const void*)&k_crit_reg<6>,  (const void*)&k_crit_reg<7>,
       (const void*)&k_crit_reg<8>,  (const void*)&k_crit_reg<9>,  (const void*)&k_crit_reg<10>,
-      (const void*)&k_crit_reg<11>, (const void*)&k_crit_reg<12>, (const void*)&k_crit_reg<13>,
-      (const void*)&k_crit_reg<14>, (const void*)&k_crit_reg<15>, (const void*)&k_crit_reg16};
+      (const void*)&k_crit_reg<11>, (const void*)&k_crit_reg<12>, (const void*)&k_crit_wide<13>,
+      (const void*)&k_crit_wide<14>, (const void*)&k_crit_wide<15>, (const void*)&k_crit_wide<16>};
   const void* fn = fns[n - 5];
   const int wg = crit_reg_wg(n);
   const int gpb = wg >> (n - crit_reg_rb(n));  // groups (masks in flight) per workgroup

@@ -1347,28 +1347,23 @@ __global__ __launch_bounds__(256) void k_criteria(const CritParams p) {
 }
 
 // ---------------------------------------------------------------------------
-// Component criteria, register-blocked (5 <= n <= 15, needs the bit-sliced
-// words F).  A group of GL lanes owns one mask at a time and each lane holds
-// R = 2^RB int32 values (RB = max(5, ceil(n/2)) up to n = 12, RB = 6 above;
-// at n = 15 the group is a whole workgroup of 512 lanes, its 2^15 entries
-// filling 136 KiB of LDS at the exchanges).
-// Layouts of the 2^n entries (register j of lane l):
+// Component criteria, register-blocked (5 <= n <= 12, needs the bit-sliced
+// words F; k_crit_wide below takes n = 13 .. 16).  A group of GL = 2^(n-RB)
+// lanes owns one mask at a time and each lane holds R = 2^RB int32 values
+// (RB = max(5, ceil(n/2))).  Two layouts of the 2^n entries (register j of
+// lane l):
 //   A: entry (l << RB) | j            bits 0..RB-1 in registers
-//   B: entry (j << LB) | l            bits LB..n-1 in registers (n <= 12,
-//                                     LB = n - RB)
-//   for n = 13 .. 15 (RB = 6), between them
-//   M: entry (l_hi << 12) | (j << 6) | l_lo, l = (l_hi, l_lo): bits 6..11
-//   and C: entry (j << (n-6)) | l     bits n-6..n-1
+//   B: entry (j << LB) | l            bits LB..n-1 in registers (LB = n - RB)
 // The transforms are products of commuting per-bit stages, so each runs the
 // stages of whatever bits its current layout holds in registers:
-//   first transform A -> (M ->) B/C: popcount stages over bits 0..4 (bias -16:
-//     the values are u = -W/2 from the start), then the register stages;
-//   v = u^2 = (W/2)^2 (24-bit multiply, |u| <= 2^14);
-//   second transform back to A, giving V(d) = 2^(n-2) r(d).
-// Exchanges go through LDS rows of R + 4 words holding 64 (or R) consecutive
-// entries: layout A moves 16-byte quads of its own row (the padding puts the
-// rows of consecutive lanes on different banks), the other layouts single
-// words at (lane + a constant per register), conflict-free.
+//   first transform A -> B: popcount stages over bits 0..4 (bias -16: the
+//     values are u = -W/2 from the start), then the register stages;
+//   v = u^2 = (W/2)^2 (24-bit multiply, |u| <= 2^11);
+//   second transform B -> A, giving V(d) = 2^(n-2) r(d).
+// Exchanges go through LDS rows of R + 4 words: layout A moves 16-byte quads
+// of its own row (the padding puts the rows of consecutive lanes on
+// different banks), layout B single words at (lane + a constant per
+// register), conflict-free.
 // Reductions: max v gives max|W|; for the smallest weight of a nonzero value
 // the registers are OR-ed by the weight of their index (a compile-time
 // constant) and the lane adds the weight of its own bits.
@@ -1386,14 +1381,15 @@ struct CritRegParams {
   int32_t* pcwt;
 };
 
-// register bits per lane of the register-blocked criteria kernel, and its
-// workgroup size (host and device)
+// register bits per lane and workgroup size of the register-blocked criteria
+// kernels (host and device): k_crit_reg up to n = 12, k_crit_wide (64 values
+// per lane, one workgroup of 2^(n-6) lanes per mask) from n = 13
 __host__ __device__ constexpr int crit_reg_rb(int n) { return n > 12 ? 6 : ((n + 1) / 2 > 5 ? (n + 1) / 2 : 5); }
-__host__ __device__ constexpr int crit_reg_wg(int n) { return (1 << (n - crit_reg_rb(n))) > 256 ? (1 << (n - crit_reg_rb(n))) : 256; }
+__host__ __device__ constexpr int crit_reg_wg(int n) { return n > 12 ? (1 << (n - 6)) : 256; }
 
 template <int N>
 struct CritShape {
-  static constexpr bool THREE = N > 12;         // layouts A, M, C
+  static_assert(N >= 5 && N <= 12, "k_crit_wide takes n > 12");
   static constexpr int RB = crit_reg_rb(N);
   static constexpr int LB = N - RB;
   static constexpr int R = 1 << RB;
@@ -1483,7 +1479,6 @@ __device__ __forceinline__ void get_rows(const int32_t* buf, int l, int32_t* v) 
 template <int N>
 __global__ __launch_bounds__(crit_reg_wg(N)) void k_crit_reg(const CritRegParams p) {
   using C = CritShape<N>;
-  constexpr bool THREE = C::THREE;
   constexpr int RB = C::RB, LB = C::LB, R = C::R, GL = C::GL, WPL = C::WPL, GPB = C::GPB, ROW = C::ROW;
   __shared__ __attribute__((aligned(16))) int32_t lds[GPB * C::GWORDS];
   __shared__ int xr[GPB][GL > 64 ? GL / 64 : 1];
@@ -1497,8 +1492,6 @@ __global__ __launch_bounds__(crit_reg_wg(N)) void k_crit_reg(const CritRegParams
   const long long kend = 1LL << p.m;
   const long long kfirst = 1 + ((long long)blockIdx.x * GPB + grp) * p.chunk;
   const int lw = __builtin_popcount(l);
-  // M layout: lane (l_hi, l_lo) = (l >> 6, l & 63) holds entry (l_hi << 12) | (j << 6) | l_lo
-  const int mbase = THREE ? at(((l >> 6) << 12) | (l & 63)) : 0;
 
   // this group's share of the aggregates, folded per workgroup at the end
   int g_nl = 1 << (N - 1), g_unb = 0, g_mw = N + 1, g_ac = 0, g_pw = N + 1;
@@ -1537,28 +1530,12 @@ __global__ __launch_bounds__(crit_reg_wg(N)) void k_crit_reg(const CritRegParams
     reg_stages<R, 5, RB>(v);
     put_rows<R, ROW>(buf, l, v);
     group_sync<GL>();
-    if constexpr (THREE) {
-      // ---- A -> M: bits 6..11
+    // ---- A -> B: bits RB..n-1 = register bits RB-LB..RB-1
 #pragma unroll
-      for (int j = 0; j < R; ++j) v[j] = buf[mbase + j * ROW];
-      group_sync<GL>();
-      reg_stages<R, 0, 6>(v);
-#pragma unroll
-      for (int j = 0; j < R; ++j) buf[mbase + j * ROW] = v[j];
-      group_sync<GL>();
-      // ---- M -> C: bits 12..n-1 = register bits 18-n..5
-#pragma unroll
-      for (int j = 0; j < R; ++j) v[j] = buf[at((j << (N - 6)) | l)];
-      group_sync<GL>();
-      reg_stages<R, 18 - N, 6>(v);
-    } else {
-      // ---- A -> B: bits RB..n-1 = register bits RB-LB..RB-1
-#pragma unroll
-      for (int j = 0; j < R; ++j) v[j] = buf[at(j << LB) + l];
-      group_sync<GL>();
-      reg_stages<R, RB - LB, RB>(v);
-    }
-    // u = -W/2 at a = (j << LB) | l (both B and C)
+    for (int j = 0; j < R; ++j) v[j] = buf[at(j << LB) + l];
+    group_sync<GL>();
+    reg_stages<R, RB - LB, RB>(v);
+    // u = -W/2 at a = (j << LB) | l
     const int w0 = -2 * v[0];  // W(0, b) (lane l = 0)
     uint32_t ci[RB + 1];
 #pragma unroll
@@ -1576,28 +1553,15 @@ __global__ __launch_bounds__(crit_reg_wg(N)) void k_crit_reg(const CritRegParams
     int mw = first_class<RB>(ci, l == 0) + lw;
     mxsq = crit_group_reduce<GL, true>(mxsq, xr[grp], l);
     mw = crit_group_reduce<GL, false>(mw, xr[grp], l);
-    // ---- second transform: all register bits of B / C
+    // ---- second transform: all register bits of B (bits LB..n-1)
     reg_stages<R, 0, RB>(v);
-    if constexpr (THREE) {
-      // ---- C -> M: bits 6..n-7 = register bits 0..n-13
 #pragma unroll
-      for (int j = 0; j < R; ++j) buf[at((j << (N - 6)) | l)] = v[j];
-      group_sync<GL>();
-#pragma unroll
-      for (int j = 0; j < R; ++j) v[j] = buf[mbase + j * ROW];
-      group_sync<GL>();
-      reg_stages<R, 0, N - 12>(v);
-#pragma unroll
-      for (int j = 0; j < R; ++j) buf[mbase + j * ROW] = v[j];
-    } else {
-#pragma unroll
-      for (int j = 0; j < R; ++j) buf[at(j << LB) + l] = v[j];
-    }
+    for (int j = 0; j < R; ++j) buf[at(j << LB) + l] = v[j];
     group_sync<GL>();
     get_rows<R, ROW>(buf, l, v);
     group_sync<GL>();
-    // ---- layout A: the bits not yet done (0..LB-1, or 0..5); V(d) at d = (l << RB) | j
-    reg_stages<R, 0, THREE ? 6 : LB>(v);
+    // ---- layout A: the bits not yet done (0..LB-1); V(d) at d = (l << RB) | j
+    reg_stages<R, 0, LB>(v);
     if (l == 0) v[0] = 0;  // d = 0 is not a direction
     uint32_t pc[RB + 1];
 #pragma unroll
@@ -1618,7 +1582,7 @@ __global__ __launch_bounds__(crit_reg_wg(N)) void k_crit_reg(const CritRegParams
     if (pw > N) pw = N + 1;
     if (l == 0 && valid) {
       const long long b = gray(k);
-      const int umax = (int)rintf(sqrtf((float)mxsq));  // mxsq is a perfect square <= 2^28
+      const int umax = (int)rintf(sqrtf((float)mxsq));  // mxsq is a perfect square <= 2^22
       if (p.w0) p.w0[b] = w0;
       if (p.minwt) p.minwt[b] = mw;
       if (p.acmax) p.acmax[b] = ac;
@@ -1658,30 +1622,45 @@ __global__ __launch_bounds__(crit_reg_wg(N)) void k_crit_reg(const CritRegParams
 }
 
 // ---------------------------------------------------------------------------
-// Component criteria at n = 16, register-blocked: one workgroup of 1024 lanes
-// (16 waves) per mask, 64 int32 values per lane (the whole 2^16 entries live
-// in registers), layouts as in k_crit_reg:
+// Component criteria at n = 13 .. 16, register-blocked: one workgroup of
+// 2^(n-6) lanes (2 .. 16 waves) per mask, 64 int32 values per lane (the
+// whole 2^n entries live in registers), layouts as in k_crit_reg:
 //   A: lane l holds entry (l << 6) | j                      bits 0..5
 //   M: lane (w, i) = (l >> 6, l & 63) holds (w << 12) | (j << 6) | i   bits 6..11
-//   C: lane l holds (P(j) << 10) | l                        bits 10..15
-// with P putting register bit 0 on entry bit 10, bits 1..4 on 12..15 and
-// bit 5 on 11.  A <-> M stays inside each wave (its 2^12 entries): the 16
-// waves take two turns over eight padded 17 KiB blocks, and the waves of the
+//   C: lane l holds (P(j) << (n-6)) | l                     bits n-6..n-1
+// with P putting register bit 5 on entry bit 11 and bits 0..4 on the other
+// five, in order.  A <-> M stays inside each wave (its 2^12 entries): the
+// waves take two turns over padded 17 KiB LDS blocks, and the waves of the
 // first turn run their stages while the second turn exchanges.  M <-> C
-// crosses waves and runs in two rounds of 2^15 entries (128 KiB), split on
-// entry bit 11, which is register bit 5 in both M and C, so each round
-// empties and refills the same 32 registers.
+// crosses waves and runs in two rounds of 2^(n-1) entries, split on entry
+// bit 11, which is register bit 5 in both M and C, so each round empties and
+// refills the same 32 registers.  LDS is 136 / 68 / 34 / 17 KiB for
+// n = 16 / 15 / 14 / 13: 16 waves per CU, <= 128 VGPRs each.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int crit16_p(int j) { return (j & 1) | (((j >> 5) & 1) << 1) | (((j >> 1) & 15) << 2); }
+// Entry of C register jj (bits 0..4 of the register index; bit 5 is the
+// round) without the lane part, with entry bit 11 taken out.
+template <int N>
+__host__ __device__ constexpr int crit_c_entry(int jj) {
+  int x = 0;
+  for (int k = 0, off = 0; k < 5; ++k, ++off) {
+    if (off == 17 - N) ++off;  // the offset of entry bit 11 belongs to register bit 5
+    if ((jj >> k) & 1) x |= 1 << (N - 6 + off);
+  }
+  return ((x >> 12) << 11) | (x & 0x7FF);
+}
 
-__global__ __launch_bounds__(1024) void k_crit_reg16(const CritRegParams p) {
-  constexpr int N = 16, R = 64, ROW = 68;
-  __shared__ __attribute__((aligned(16))) int32_t lds[8 * 64 * ROW];  // 136 KiB
-  __shared__ int xr[16];
+template <int N>
+__global__ __launch_bounds__(1 << (N - 6), 4) void k_crit_wide(const CritRegParams p) {  // four waves per SIMD
+  constexpr int R = 64, ROW = 68;
+  constexpr int NWAV = 1 << (N - 12);  // waves per mask
+  constexpr int NB = NWAV / 2;         // LDS blocks: waves per turn of the A <-> M exchange
+  constexpr int LDS_WORDS = (NB * 64 * ROW > (1 << (N - 1))) ? NB * 64 * ROW : (1 << (N - 1));
+  __shared__ __attribute__((aligned(16))) int32_t lds[LDS_WORDS];
+  __shared__ int xr[NWAV];
   const int l = threadIdx.x;
   const int w = __builtin_amdgcn_readfirstlane(l >> 6), i = l & 63;  // wave index: uniform, scalar branches
-  const bool first_turn = w < 8;
-  int32_t* blk = lds + (w & 7) * 64 * ROW;  // this wave's block for A <-> M
+  const bool first_turn = w < NB;
+  int32_t* blk = lds + (w % NB) * 64 * ROW;  // this wave's block for A <-> M
   const int nwords = 1 << (N - 5);
   const long long kend = 1LL << p.m;
   const long long kfirst = 1 + (long long)blockIdx.x * p.chunk;
@@ -1713,7 +1692,7 @@ __global__ __launch_bounds__(1024) void k_crit_reg16(const CritRegParams p) {
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
   };
-  // M <-> C round r (entry bit 11 = r): entries without bit 11, 2^15 words
+  // M <-> C round r (entry bit 11 = r): entries without bit 11, 2^(n-1) words
   auto put_m_round = [&](const int32_t* v, int r) {
 #pragma unroll
     for (int jj = 0; jj < 32; ++jj) lds[(w << 11) | (jj << 6) | i] = v[32 * r + jj];
@@ -1724,11 +1703,11 @@ __global__ __launch_bounds__(1024) void k_crit_reg16(const CritRegParams p) {
   };
   auto put_c_round = [&](const int32_t* v, int r) {
 #pragma unroll
-    for (int jj = 0; jj < 32; ++jj) lds[(((jj >> 1) & 15) << 11) | ((jj & 1) << 10) | l] = v[32 * r + jj];
+    for (int jj = 0; jj < 32; ++jj) lds[crit_c_entry<N>(jj) + l] = v[32 * r + jj];
   };
   auto get_c_round = [&](int32_t* v, int r) {
 #pragma unroll
-    for (int jj = 0; jj < 32; ++jj) v[32 * r + jj] = lds[(((jj >> 1) & 15) << 11) | ((jj & 1) << 10) | l];
+    for (int jj = 0; jj < 32; ++jj) v[32 * r + jj] = lds[crit_c_entry<N>(jj) + l];
   };
 
   for (long long step = 0; step < p.chunk; ++step) {
@@ -1763,8 +1742,8 @@ __global__ __launch_bounds__(1024) void k_crit_reg16(const CritRegParams p) {
     put_m_round(v, 1);
     __syncthreads();
     get_c_round(v, 1);
-    reg_stages<R, 1, 5>(v);  // C: bits 12..15
-    // u = -W/2 at a = (P(j) << 10) | l
+    reg_stages<R, 17 - N, 5>(v);  // C: bits 12..n-1
+    // u = -W/2 at a = (P(j) << (n-6)) | l
     const int w0 = -2 * v[0];  // lane 0
     uint32_t ci[7] = {0, 0, 0, 0, 0, 0, 0};
     int mxsq = 0;
@@ -1778,9 +1757,9 @@ __global__ __launch_bounds__(1024) void k_crit_reg16(const CritRegParams p) {
     // group results of the first transform now (a convergent reduction the
     // compiler cannot sink past the second transform with all the squares)
     int mw = first_class<6>(ci, l == 0) + lw;
-    mxsq = crit_group_reduce<1024, true>(mxsq, xr, l);
-    mw = crit_group_reduce<1024, false>(mw, xr, l);
-    // ---- second transform: C bits 10..15, M bits 6..9, A bits 0..5
+    mxsq = crit_group_reduce<64 * NWAV, true>(mxsq, xr, l);
+    mw = crit_group_reduce<64 * NWAV, false>(mw, xr, l);
+    // ---- second transform: C bits n-6..n-1, M bits 6..n-7, A bits 0..5
     reg_stages<R, 0, 6>(v);
     __syncthreads();
     put_c_round(v, 0);
@@ -1790,7 +1769,7 @@ __global__ __launch_bounds__(1024) void k_crit_reg16(const CritRegParams p) {
     put_c_round(v, 1);
     __syncthreads();
     get_m_round(v, 1);
-    reg_stages<R, 0, 4>(v);
+    reg_stages<R, 0, N - 12>(v);
     __syncthreads();
     if (first_turn) { put_m(v); wsync(); get_a(v); }
     __syncthreads();
@@ -1808,8 +1787,8 @@ __global__ __launch_bounds__(1024) void k_crit_reg16(const CritRegParams p) {
     }
     int pw = first_class<6>(pc, l == 0) + lw;
     int ac = max(vmax, -vmin) >> (N - 2);
-    ac = crit_group_reduce<1024, true>(ac, xr, l);
-    pw = crit_group_reduce<1024, false>(pw, xr, l);
+    ac = crit_group_reduce<64 * NWAV, true>(ac, xr, l);
+    pw = crit_group_reduce<64 * NWAV, false>(pw, xr, l);
     if (mw > N) mw = N + 1;
     if (pw > N) pw = N + 1;
     if (l == 0 && valid) {
