@@ -332,17 +332,6 @@ sbox_status run_single(const void* S, int n, int m, int eb, int32_t* maxabs, int
     if (s) return s;
     return run_big(S, n, m, eb, maxabs, nl, ws, ws_bytes, tun, st, queue);
   }
-  // bit-sliced component words
-  {
-    const void* S_ = S;
-    int n_ = n, m_ = m, nw_ = nwords;
-    uint32_t* F_ = F;
-    void* args[] = {(void*)&S_, &n_, &m_, &F_, &nw_};
-    const void* fn = eb == 1 ? (const void*)&k_bitslice<1> : eb == 2 ? (const void*)&k_bitslice<2>
-                                                                     : (const void*)&k_bitslice<4>;
-    s = launch(fn, dim3((nwords + 255) / 256), dim3(256), args, st);
-    if (s) return s;
-  }
   JobDesc jd{};
   jd.S = S;
   jd.F = F;
@@ -355,12 +344,14 @@ sbox_status run_single(const void* S, int n, int m, int eb, int32_t* maxabs, int
   jd.nwords = nwords;
   jd.s_elem_bytes = eb;
   jd.wscale = wscale;
-  // init: queue counters, NL, maxabs[0], b = 0 spectrum row
+  // one launch: start values (queue counters, NL, maxabs[0], b = 0 spectrum
+  // row) in workgroup 0, bit-sliced component words in the others
   {
-    const JobDesc* nulljobs = nullptr;
-    int one = 1, nq = 64, lay = layout;
-    void* args[] = {(void*)&nulljobs, &jd, &one, &queue, &nq, &lay};
-    s = launch((const void*)&k_init_jobs, dim3(1), dim3(256), args, st);
+    int nq = 64, lay = layout;
+    void* args[] = {&jd, &queue, &nq, &lay};
+    const void* fn = eb == 1 ? (const void*)&k_prep_single<1> : eb == 2 ? (const void*)&k_prep_single<2>
+                                                                        : (const void*)&k_prep_single<4>;
+    s = launch(fn, dim3(1 + (nwords + 255) / 256), dim3(256), args, st);
     if (s) return s;
   }
 
@@ -984,12 +975,13 @@ sbox_status criteria_reg(const void* S, int n, int m, int eb, int32_t* summary, 
   uint32_t* F = reinterpret_cast<uint32_t*>(ws);
   const int nwords = 1 << (n - 5);
   {
+    // start values (workgroup 0) and the bit-sliced table, one launch
     const void* S_ = S;
     int n_ = n, m_ = m, nw_ = nwords;
-    void* args[] = {(void*)&S_, &n_, &m_, &F, &nw_};
-    const void* fn = eb == 1 ? (const void*)&k_bitslice<1> : eb == 2 ? (const void*)&k_bitslice<2>
-                                                                    : (const void*)&k_bitslice<4>;
-    s = launch(fn, dim3((nwords + 255) / 256), dim3(256), args, st);
+    void* args[] = {(void*)&S_, &n_, &m_, &F, &nw_, &summary, &w0, &minwt, &acmax, &pcwt};
+    const void* fn = eb == 1 ? (const void*)&k_crit_prep<1> : eb == 2 ? (const void*)&k_crit_prep<2>
+                                                                      : (const void*)&k_crit_prep<4>;
+    s = launch(fn, dim3(1 + (nwords + 255) / 256), dim3(256), args, st);
     if (s) return s;
   }
   static const void* const fns[] = {
@@ -1038,7 +1030,7 @@ sbox_status sbox_criteria_ex(const void* S, int n, int m, int s_elem_bytes, int3
   if (s_elem_bytes != 1 && s_elem_bytes != 2 && s_elem_bytes != 4)
     return fail(SBOX_ERR_INVALID_ARG, "s_elem_bytes must be 1, 2 or 4 (got %d)", s_elem_bytes);
   // n >= 15 needs a workspace; for 5 <= n <= 14 one selects the register-blocked
-  // kernel (without one, the LDS kernel runs)
+  // kernels (without one, the LDS kernel runs)
   const bool use_ws = n >= 15 || (n >= 5 && workspace != nullptr);
   if (use_ws) {
     const size_t need = sbox_criteria_workspace_bytes(n, m);
@@ -1050,16 +1042,14 @@ sbox_status sbox_criteria_ex(const void* S, int n, int m, int s_elem_bytes, int3
   int cus = 0;
   sbox_status s = device_info(&cus);
   if (s) return s;
+  if (use_ws)  // sets the start values and finishes the summary itself
+    return criteria_reg(S, n, m, s_elem_bytes, summary, w0_per_b, minwt_per_b, acmax_per_b, pcwt_per_b,
+                        workspace, st);
   {
     int n_ = n;
     void* args[] = {&summary, &n_, &w0_per_b, &minwt_per_b, &acmax_per_b, &pcwt_per_b};
     s = launch((const void*)&k_criteria_init, dim3(1), dim3(64), args, st);
     if (s) return s;
-  }
-  if (use_ws) {
-    // finishes the summary itself
-    return criteria_reg(S, n, m, s_elem_bytes, summary, w0_per_b, minwt_per_b, acmax_per_b, pcwt_per_b,
-                        workspace, st);
   }
   const void* fn = s_elem_bytes == 1 ? (const void*)&k_criteria<1>
                  : s_elem_bytes == 2 ? (const void*)&k_criteria<2> : (const void*)&k_criteria<4>;

@@ -1192,13 +1192,6 @@ __device__ void bitslice_words(const void* S, int n, int m, uint32_t* F, int nwo
   }
 }
 
-// Single table: one thread per word.
-template <int EB>
-__global__ __launch_bounds__(256) void k_bitslice(const void* S, int n, int m, uint32_t* F, int nwords) {
-  const int w = blockIdx.x * blockDim.x + threadIdx.x;
-  if (w < nwords) bitslice_words<EB>(S, n, m, F, nwords, w);
-}
-
 // Bit-slicing for k_walsh_big: word w = x_lo >> B holds, at bit
 // j = x_lo_low + 2^B * x_hi, bit i of S[x_hi * 2^16 + x_lo].
 template <int EB>
@@ -1845,7 +1838,8 @@ __global__ __launch_bounds__(256) void k_crit_reg_finish(const int32_t* part, in
 }
 
 // crit[] start values; per-mask outputs at b = 0 are defined as 0.
-__global__ void k_criteria_init(int32_t* crit, int n, int32_t* w0, int32_t* minwt, int32_t* acmax, int32_t* pcwt) {
+__device__ __forceinline__ void criteria_start(int32_t* crit, int n, int32_t* w0, int32_t* minwt, int32_t* acmax,
+                                               int32_t* pcwt) {
   if (threadIdx.x == 0) {
     crit[0] = 1 << (n - 1);
     crit[1] = 0;
@@ -1860,6 +1854,23 @@ __global__ void k_criteria_init(int32_t* crit, int n, int32_t* w0, int32_t* minw
     if (acmax) acmax[0] = 0;
     if (pcwt) pcwt[0] = 0;
   }
+}
+
+__global__ void k_criteria_init(int32_t* crit, int n, int32_t* w0, int32_t* minwt, int32_t* acmax, int32_t* pcwt) {
+  criteria_start(crit, n, w0, minwt, acmax, pcwt);
+}
+
+// The criteria's start values (workgroup 0) and bit-sliced table (the others)
+// in one launch.
+template <int EB>
+__global__ __launch_bounds__(256) void k_crit_prep(const void* S, int n, int m, uint32_t* F, int nwords, int32_t* crit,
+                                                   int32_t* w0, int32_t* minwt, int32_t* acmax, int32_t* pcwt) {
+  if (blockIdx.x == 0) {
+    criteria_start(crit, n, w0, minwt, acmax, pcwt);
+    return;
+  }
+  const int w = (blockIdx.x - 1) * blockDim.x + threadIdx.x;
+  if (w < nwords) bitslice_words<EB>(S, n, m, F, nwords, w);
 }
 
 // Orders from the minimum weights: CI = minwt - 1, resiliency = CI if balanced.
@@ -1912,12 +1923,10 @@ __global__ __launch_bounds__(256) void k_transpose_slab16(const int16_t* slab, i
 // Per-call initialisation: queue counters, NL start value 2^(n-1),
 // maxabs[0] = 2^n, and the b = 0 row / column of a requested spectrum.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_init_jobs(const JobDesc* jobs, JobDesc job0, int njobs,
-                                                   int* queue, int nqueue, int layout) {
-  const int j = blockIdx.x;
-  if (j >= njobs) return;
-  const JobDesc jd = jobs ? jobs[j] : job0;
-  if (j == 0) {
+// One workgroup's share: the job's start values (and, for the first job, the
+// queue counters).
+__device__ __forceinline__ void init_job(const JobDesc& jd, bool first, int* queue, int nqueue, int layout) {
+  if (first) {
     for (int i = threadIdx.x; i < nqueue; i += blockDim.x) queue[i] = 0;
   }
   if (threadIdx.x == 0) {
@@ -1932,6 +1941,25 @@ __global__ __launch_bounds__(256) void k_init_jobs(const JobDesc* jobs, JobDesc 
       else jd.spec[a << jd.m] = v;
     }
   }
+}
+
+__global__ __launch_bounds__(256) void k_init_jobs(const JobDesc* jobs, JobDesc job0, int njobs,
+                                                   int* queue, int nqueue, int layout) {
+  const int j = blockIdx.x;
+  if (j >= njobs) return;
+  init_job(jobs ? jobs[j] : job0, j == 0, queue, nqueue, layout);
+}
+
+// A single box in one launch before its transform: workgroup 0 sets the
+// start values, the others bit-slice the table into jd.F (one word a thread).
+template <int EB>
+__global__ __launch_bounds__(256) void k_prep_single(JobDesc jd, int* queue, int nqueue, int layout) {
+  if (blockIdx.x == 0) {
+    init_job(jd, true, queue, nqueue, layout);
+    return;
+  }
+  const int w = (blockIdx.x - 1) * blockDim.x + threadIdx.x;
+  if (w < jd.nwords) bitslice_words<EB>(jd.S, jd.n, jd.m, const_cast<uint32_t*>(jd.F), jd.nwords, w);
 }
 
 // Zero `count` ints (queue counters, per-batch maxima) without a memset node.
