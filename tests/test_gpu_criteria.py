@@ -154,6 +154,45 @@ def test_criteria_16x16_permutation():
     assert summ["abs_indicator"] == int(acm[1:].max())
 
 
+def _fwht(v):
+    """Natural-order Walsh-Hadamard transform (int64), for the autocorrelation
+    r = 2^-n H(W^2) of a transform column (Wiener-Khinchin)."""
+    v = np.array(v, dtype=np.int64)
+    h = 1
+    while h < v.size:
+        v = v.reshape(-1, 2, h)
+        v = np.stack([v[:, 0] + v[:, 1], v[:, 0] - v[:, 1]], axis=1).reshape(-1)
+        h *= 2
+    return v
+
+
+def test_criteria_largest_box_sampled():
+    """n = 16, m = 24 (n + m = 40, 2^24 - 1 masks, 4,096 workgroups walking
+    long Gray runs): sampled masks against the oracle's transform column (w0,
+    CI weight) and its Wiener-Khinchin autocorrelation (absolute indicator,
+    PC weight); the summary against the per-mask arrays."""
+    n, m = 16, 24
+    S = table(n, m, 12900)
+    summ, per = B.criteria(dev_table(S, m), n, m)
+    per = {k: v.cpu().numpy() for k, v in per.items()}
+    assert summ["unbalanced"] == int(np.count_nonzero(per["w0"][1:]))
+    assert summ["abs_indicator"] == int(per["acmax"][1:].max())
+    assert summ["ci_order"] == int(per["minwt"][1:].min()) - 1
+    assert summ["pc_order"] == int(per["pcwt"][1:].min()) - 1
+    wts = np.bitwise_count(np.arange(1 << n).astype(np.uint64))
+    g = inputs.rng(12901)
+    for b in [1, (1 << m) - 1, 1 << 23, 0x5A5A5A] + [int(v) for v in g.integers(1, 1 << m, size=4)]:
+        col = oracle.walsh_column(S, n, m, b).astype(np.int64)
+        assert per["w0"][b] == col[0], b
+        nz = wts[1:][col[1:] != 0]
+        assert per["minwt"][b] == (int(nz.min()) if nz.size else n + 1), b
+        r = _fwht(col * col) >> n  # H(W^2) = 2^n r
+        assert r[0] == 1 << n
+        assert per["acmax"][b] == int(np.abs(r[1:]).max()), b
+        nzr = wts[1:][r[1:] != 0]
+        assert per["pcwt"][b] == (int(nzr.min()) if nzr.size else n + 1), b
+
+
 def test_criteria_ex_small_n_needs_no_workspace():
     import torch
     n, m = 10, 6
