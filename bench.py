@@ -160,7 +160,7 @@ def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the Walsh/NL path is built and timed on a single "
-              "MI355X (multi-GPU sharding over masks is a design note, not part of this build)",
+              "MI355X (sharding the masks over several GPUs is described, not implemented)",
               file=sys.stderr)
         sys.exit(2)
     import numpy as np
