@@ -97,13 +97,30 @@ typedef struct sbox_tuning {
  *                uint8 if m <= 8, uint16 if m <= 16, else uint32.
  *   maxabs_per_b device int32[2^m] receiving max_a |W(a,b)|, or NULL.
  *   nl           device int32[1] receiving NL (required).
- * Uses a scratch area owned by the library (one per device, grown on
- * demand with hipMalloc and kept until the process ends), so the first
- * call at a new size allocates and is not graph-capturable; use
- * sbox_walsh_nl_ex with a caller workspace for capture.
+ * Takes its scratch from the buffer that sbox_scratch_reserve set aside for
+ * this (device, stream) pair and never allocates: with no reservation, or
+ * one made for a smaller (n, m), it returns SBOX_ERR_WORKSPACE and enqueues
+ * nothing.  Calls on different streams use different scratch, so they may
+ * overlap; calls on one stream are ordered by the stream.  Capturable (a
+ * captured graph keeps the reserved buffer's address: do not replay it after
+ * a reservation on that stream grew or was released).
  */
 sbox_status sbox_walsh_nl(const void* S, int n, int m, int32_t* maxabs_per_b, int32_t* nl,
                           void* stream);
+
+/*
+ * Scratch for sbox_walsh_nl on `stream` of the current device, large
+ * enough for every box up to n x m (the fused path's workspace).  Host
+ * call; allocates device memory (hipMalloc) owned by the library, so it is
+ * not capturable (SBOX_ERR_INVALID_ARG on a capturing stream).  A
+ * reservation that is already large enough is kept as is; a smaller one is
+ * replaced after the stream has been synchronised.
+ * sbox_scratch_release synchronises the stream and frees its reservation
+ * (no-op without one).  Neither may run concurrently with a sbox_walsh_nl
+ * call on the same stream from another host thread.
+ */
+sbox_status sbox_scratch_reserve(int n, int m, void* stream);
+sbox_status sbox_scratch_release(void* stream);
 
 /*
  * Full form.
@@ -142,11 +159,16 @@ typedef struct sbox_job {
  * Many S-boxes of mixed sizes in one pass: boxes are grouped by n and each
  * group runs as one persistent launch whose workgroups pull (box, mask
  * range) items from a device work queue.  `jobs` is a host array of
- * `count` entries; its descriptors are staged through a library-owned
- * pinned host buffer and copied asynchronously, so the array may be reused
- * as soon as the call returns.  Each box's results equal those of
- * sbox_walsh_nl_ex on that box alone.  Returns SBOX_ERR_UNSUPPORTED if a
- * box has n > 16.
+ * `count` entries; its descriptors are copied into the workspace
+ * asynchronously from a library-owned pinned block that is taken again only
+ * after that copy has completed, so the array may be reused as soon as the
+ * call returns and calls on different streams do not wait for each other on
+ * the host (the pool holds up to 32 blocks per device; only when all are in
+ * flight does a call wait for the oldest).  Each box's results equal those
+ * of sbox_walsh_nl_ex on that box alone.  Not capturable, since the copy
+ * reads the pinned block at launch time: on a capturing stream it returns
+ * SBOX_ERR_INVALID_ARG (capture sbox_plan_launch instead).  Returns
+ * SBOX_ERR_UNSUPPORTED if a box has n > 16.
  */
 sbox_status sbox_walsh_nl_batched(const sbox_job* jobs, int32_t count,
                                   void* workspace, size_t workspace_bytes, void* stream);

@@ -53,7 +53,8 @@ class sbox_job(ctypes.Structure):
 
 
 # Every exported symbol of include/sbox_walsh.h.
-EXPORTS = ("sbox_walsh_nl", "sbox_walsh_nl_ex", "sbox_walsh_nl_workspace_bytes",
+EXPORTS = ("sbox_walsh_nl", "sbox_scratch_reserve", "sbox_scratch_release", "sbox_walsh_nl_ex",
+           "sbox_walsh_nl_workspace_bytes",
            "sbox_walsh_nl_batched", "sbox_batched_workspace_bytes", "sbox_plan_create",
            "sbox_plan_launch", "sbox_plan_destroy", "sbox_criteria", "sbox_criteria_ex",
            "sbox_criteria_workspace_bytes", "sbox_walsh_histogram",
@@ -73,6 +74,8 @@ def load(path: str = LIB_PATH):
     lib = ctypes.CDLL(path)
     vp, i32, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t
     lib.sbox_walsh_nl.argtypes = [vp, i32, i32, vp, vp, vp]
+    lib.sbox_scratch_reserve.argtypes = [i32, i32, vp]
+    lib.sbox_scratch_release.argtypes = [vp]
     lib.sbox_walsh_nl_ex.argtypes = [vp, i32, i32, i32, vp, vp, vp, i32, vp, sz,
                                      ctypes.POINTER(sbox_tuning), vp]
     lib.sbox_walsh_nl_workspace_bytes.argtypes = [i32, i32, i32]
@@ -101,8 +104,8 @@ def load(path: str = LIB_PATH):
     lib.sbox_avalanche_workspace_bytes.restype = sz
     lib.sbox_last_error.restype = ctypes.c_char_p
     lib.sbox_version.restype = ctypes.c_char_p
-    for f in ("sbox_walsh_nl", "sbox_walsh_nl_ex", "sbox_walsh_nl_batched", "sbox_plan_create",
-              "sbox_plan_launch"):
+    for f in ("sbox_walsh_nl", "sbox_scratch_reserve", "sbox_scratch_release", "sbox_walsh_nl_ex",
+              "sbox_walsh_nl_batched", "sbox_plan_create", "sbox_plan_launch"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -121,6 +124,14 @@ def _check(status: int):
 
 def sbox_walsh_nl(S: int, n: int, m: int, maxabs_per_b: int, nl: int, stream: int) -> int:
     return load().sbox_walsh_nl(S, n, m, maxabs_per_b, nl, stream)
+
+
+def sbox_scratch_reserve(n: int, m: int, stream: int) -> int:
+    return load().sbox_scratch_reserve(n, m, stream)
+
+
+def sbox_scratch_release(stream: int) -> int:
+    return load().sbox_scratch_release(stream)
 
 
 def sbox_walsh_nl_ex(S: int, n: int, m: int, s_elem_bytes: int, maxabs_per_b: int, nl: int,

@@ -729,20 +729,93 @@ sbox_status launch_batch(const BatchLayout& L, void* ws, hipStream_t st) {
   return SBOX_OK;
 }
 
-// ------------------------------------------------- pinned staging buffer ---
+// ------------------------------------------------- pinned staging blocks ---
+// sbox_walsh_nl_batched copies its descriptor table to the device from a
+// pinned block; a block is taken again only once the event recorded after
+// its copy has completed, so calls on different streams never wait on each
+// other on the host (only when every block of the pool is still in flight).
+struct StageBlock {
+  void* host = nullptr;
+  size_t bytes = 0;
+  hipEvent_t evt = nullptr;
+  int dev = -1;
+};
+constexpr size_t kStageMaxBlocks = 32;
+constexpr size_t kStageMinBytes = 64 << 10;
 std::mutex g_stage_mu;
-void* g_stage = nullptr;
-size_t g_stage_bytes = 0;
-hipEvent_t g_stage_evt = nullptr;
-bool g_stage_pending = false;
+std::vector<StageBlock> g_stage;
 
-// ------------------------------------------------- library-owned scratch ---
-struct Scratch {
+// A block of at least `bytes` on device `dev` whose last copy has finished
+// (waits only when all kStageMaxBlocks blocks are in flight).
+sbox_status acquire_stage(int dev, size_t bytes, StageBlock** out) {
+  StageBlock* fit = nullptr;    // free and large enough
+  StageBlock* spare = nullptr;  // free but too small (replaced when the pool is full)
+  size_t mine = 0;
+  for (StageBlock& b : g_stage) {
+    if (b.dev != dev) continue;
+    ++mine;
+    const hipError_t q = hipEventQuery(b.evt);
+    if (q == hipErrorNotReady) continue;
+    if (q != hipSuccess) return fail(SBOX_ERR_HIP, "hipEventQuery: %s", hipGetErrorString(q));
+    if (b.bytes >= bytes && (!fit || b.bytes < fit->bytes)) fit = &b;
+    if (b.bytes < bytes) spare = &b;
+  }
+  if (!fit && mine >= kStageMaxBlocks) {
+    if (!spare) {  // every block is in flight: wait for one of them
+      for (StageBlock& b : g_stage)
+        if (b.dev == dev) {
+          spare = &b;
+          break;
+        }
+      HIP_TRY(hipEventSynchronize(spare->evt));
+    }
+    if (spare->bytes >= bytes) {
+      fit = spare;
+    } else {
+      HIP_TRY(hipHostFree(spare->host));
+      spare->host = nullptr;
+      spare->bytes = 0;
+      HIP_TRY(hipHostMalloc(&spare->host, std::max(bytes, kStageMinBytes), hipHostMallocDefault));
+      spare->bytes = std::max(bytes, kStageMinBytes);
+      fit = spare;
+    }
+  }
+  if (!fit) {
+    StageBlock b;
+    b.dev = dev;
+    b.bytes = std::max(bytes, kStageMinBytes);
+    HIP_TRY(hipHostMalloc(&b.host, b.bytes, hipHostMallocDefault));
+    const hipError_t e = hipEventCreateWithFlags(&b.evt, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      (void)hipHostFree(b.host);
+      return fail(SBOX_ERR_HIP, "hipEventCreateWithFlags: %s", hipGetErrorString(e));
+    }
+    g_stage.push_back(b);
+    fit = &g_stage.back();
+  }
+  *out = fit;
+  return SBOX_OK;
+}
+
+sbox_status refuse_capture(hipStream_t st, const char* what) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  HIP_TRY(hipStreamIsCapturing(st, &cs));
+  if (cs != hipStreamCaptureStatusNone)
+    return fail(SBOX_ERR_INVALID_ARG, "%s cannot be captured into a graph (%s)", what,
+                cs == hipStreamCaptureStatusActive ? "the stream is capturing" : "the capture was invalidated");
+  return SBOX_OK;
+}
+
+// ---------------------------------------- short-form scratch per stream ---
+// sbox_walsh_nl takes its scratch (queue counters, bit-sliced words) from a
+// buffer reserved ahead of time for its (device, stream) pair; it never
+// allocates, and calls on different streams never share scratch.
+struct StreamScratch {
   void* ptr = nullptr;
   size_t bytes = 0;
 };
 std::mutex g_scratch_mu;
-std::map<int, Scratch> g_scratch;
+std::map<std::pair<int, uintptr_t>, StreamScratch> g_scratch;
 
 }  // namespace
 
@@ -898,6 +971,45 @@ sbox_status sbox_avalanche(const void* S, int n, int m, int s_elem_bytes, int32_
   }
 }
 
+sbox_status sbox_scratch_reserve(int n, int m, void* stream) {
+  sbox_status s = check_nm(n, m);
+  if (s) return s;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  s = refuse_capture(st, "sbox_scratch_reserve");
+  if (s) return s;
+  const size_t need = sbox_walsh_nl_workspace_bytes(n, m, 0);
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  StreamScratch& sc = g_scratch[{dev, reinterpret_cast<uintptr_t>(stream)}];
+  if (sc.bytes >= need) return SBOX_OK;
+  if (sc.ptr) {
+    // earlier calls on this stream may still read the old buffer
+    HIP_TRY(hipStreamSynchronize(st));
+    HIP_TRY(hipFree(sc.ptr));
+    sc.ptr = nullptr;
+    sc.bytes = 0;
+  }
+  HIP_TRY(hipMalloc(&sc.ptr, need));
+  sc.bytes = need;
+  return SBOX_OK;
+}
+
+sbox_status sbox_scratch_release(void* stream) {
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  sbox_status s = refuse_capture(st, "sbox_scratch_release");
+  if (s) return s;
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch.find({dev, reinterpret_cast<uintptr_t>(stream)});
+  if (it == g_scratch.end()) return SBOX_OK;
+  HIP_TRY(hipStreamSynchronize(st));
+  HIP_TRY(hipFree(it->second.ptr));
+  g_scratch.erase(it);
+  return SBOX_OK;
+}
+
 sbox_status sbox_walsh_nl(const void* S, int n, int m, int32_t* maxabs_per_b, int32_t* nl, void* stream) {
   sbox_status s = check_nm(n, m);
   if (s) return s;
@@ -905,24 +1017,19 @@ sbox_status sbox_walsh_nl(const void* S, int n, int m, int32_t* maxabs_per_b, in
   const size_t need = sbox_walsh_nl_workspace_bytes(n, m, 0);
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
-  void* ws = nullptr;
+  StreamScratch sc;
   {
     std::lock_guard<std::mutex> lk(g_scratch_mu);
-    Scratch& sc = g_scratch[dev];
-    if (sc.bytes < need) {
-      if (sc.ptr) {
-        HIP_TRY(hipDeviceSynchronize());
-        HIP_TRY(hipFree(sc.ptr));
-        sc.ptr = nullptr;
-        sc.bytes = 0;
-      }
-      HIP_TRY(hipMalloc(&sc.ptr, need));
-      sc.bytes = need;
-    }
-    ws = sc.ptr;
-    return sbox_walsh_nl_ex(S, n, m, elem_bytes_for(m), maxabs_per_b, nl, nullptr, 0, ws, sc.bytes, nullptr,
-                            stream);
+    auto it = g_scratch.find({dev, reinterpret_cast<uintptr_t>(stream)});
+    if (it != g_scratch.end()) sc = it->second;
   }
+  if (sc.bytes < need)
+    return fail(SBOX_ERR_WORKSPACE,
+                "no scratch of %zu bytes reserved for this stream on device %d (have %zu): call "
+                "sbox_scratch_reserve(%d, %d, stream) first",
+                need, dev, sc.bytes, n, m);
+  return sbox_walsh_nl_ex(S, n, m, elem_bytes_for(m), maxabs_per_b, nl, nullptr, 0, sc.ptr, sc.bytes, nullptr,
+                          stream);
 }
 
 size_t sbox_batched_workspace_bytes(const sbox_job* jobs, int32_t count) {
@@ -944,27 +1051,22 @@ sbox_status sbox_walsh_nl_batched(const sbox_job* jobs, int32_t count, void* wor
   if (!workspace || workspace_bytes < L.ws_bytes)
     return fail(SBOX_ERR_WORKSPACE, "workspace of %zu bytes, need %zu", workspace_bytes, L.ws_bytes);
   if (reinterpret_cast<uintptr_t>(workspace) & 255) return fail(SBOX_ERR_INVALID_ARG, "workspace not 256-byte aligned");
-  bind_batch(L, workspace);
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  s = refuse_capture(st, "sbox_walsh_nl_batched (its descriptors are staged per call; capture sbox_plan_launch)");
+  if (s) return s;
+  bind_batch(L, workspace);
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
   {
     std::lock_guard<std::mutex> lk(g_stage_mu);
     const size_t bytes = L.descs.size() * sizeof(JobDesc);
-    if (g_stage_pending) {
-      HIP_TRY(hipEventSynchronize(g_stage_evt));
-      g_stage_pending = false;
-    }
-    if (g_stage_bytes < bytes) {
-      if (g_stage) HIP_TRY(hipHostFree(g_stage));
-      g_stage = nullptr;
-      g_stage_bytes = 0;
-      HIP_TRY(hipHostMalloc(&g_stage, bytes, hipHostMallocDefault));
-      g_stage_bytes = bytes;
-    }
-    if (!g_stage_evt) HIP_TRY(hipEventCreateWithFlags(&g_stage_evt, hipEventDisableTiming));
-    std::memcpy(g_stage, L.descs.data(), bytes);
-    HIP_TRY(hipMemcpyAsync(reinterpret_cast<char*>(workspace) + kQueueBytes, g_stage, bytes, hipMemcpyHostToDevice, st));
-    HIP_TRY(hipEventRecord(g_stage_evt, st));
-    g_stage_pending = true;
+    StageBlock* blk = nullptr;
+    s = acquire_stage(dev, bytes, &blk);
+    if (s) return s;
+    std::memcpy(blk->host, L.descs.data(), bytes);
+    HIP_TRY(hipMemcpyAsync(reinterpret_cast<char*>(workspace) + kQueueBytes, blk->host, bytes,
+                           hipMemcpyHostToDevice, st));
+    HIP_TRY(hipEventRecord(blk->evt, st));
   }
   return launch_batch(L, workspace, st);
 }

@@ -92,6 +92,11 @@ struct KParams {
   unsigned long long* hist_over;  // values with |W|/2 >= kHistBins - 1 seen by kHist
 };
 
+// The host passes these structs by value as kernel arguments; both
+// compilation passes (host and gfx950) must see the same layout.
+static_assert(sizeof(JobDesc) == 72 && alignof(JobDesc) == 8, "JobDesc layout");
+static_assert(sizeof(KParams) == 168 && __builtin_offsetof(KParams, hist_over) == 160, "KParams layout");
+
 typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));
 typedef __attribute__((address_space(1))) int32_t gint32;  // global memory
 typedef __attribute__((address_space(1))) int16_t gint16;

@@ -208,3 +208,15 @@ def test_criteria_ex_small_n_workspace_checked_when_given(lib):
     need = B.sbox_criteria_workspace_bytes(12, 8)
     assert B.sbox_criteria_ex(4096, 12, 8, 1, 8192, 0, 0, 0, 0, 4096, need - 1, 0) == B.SBOX_ERR_WORKSPACE
     assert B.sbox_criteria_ex(4096, 12, 8, 1, 8192, 0, 0, 0, 0, 4096 + 16, need, 0) == B.SBOX_ERR_INVALID_ARG
+
+
+def test_short_form_and_reservation_validate_on_the_host(lib):
+    """The short form and the scratch reservation check their arguments
+    before any HIP call (the GPU tests cover the missing-reservation path)."""
+    assert B.sbox_walsh_nl(0, 8, 8, 0, 8192, 0) == B.SBOX_ERR_INVALID_ARG
+    assert B.sbox_walsh_nl(4096, 8, 8, 0, 0, 0) == B.SBOX_ERR_INVALID_ARG
+    assert B.sbox_walsh_nl(4096, 0, 8, 0, 8192, 0) == B.SBOX_ERR_UNSUPPORTED
+    assert B.sbox_walsh_nl(4096, 20, 21, 0, 8192, 0) == B.SBOX_ERR_UNSUPPORTED
+    assert B.sbox_scratch_reserve(0, 4, 0) == B.SBOX_ERR_UNSUPPORTED
+    assert B.sbox_scratch_reserve(25, 1, 0) == B.SBOX_ERR_UNSUPPORTED
+    assert "unsupported" in B.sbox_last_error()

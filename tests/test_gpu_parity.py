@@ -180,17 +180,31 @@ def test_large_n_tuning(n, m, chunk, grid):
 
 
 def test_short_form_entry_point():
+    """The short form never allocates: without a reservation for its stream
+    it refuses; after sbox_scratch_reserve it runs on the reserved scratch."""
     import torch
     S = table(10, 9, 9000)
     t = dev_table(S, 9)
     mx = torch.empty(1 << 9, dtype=torch.int32, device="cuda")
-    nl = torch.empty(1, dtype=torch.int32, device="cuda")
-    st = B.sbox_walsh_nl(t.data_ptr(), 10, 9, mx.data_ptr(), nl.data_ptr(),
-                         int(torch.cuda.current_stream().cuda_stream))
-    assert st == B.SBOX_OK
+    nl = torch.full((1,), -5, dtype=torch.int32, device="cuda")
+    s = torch.cuda.Stream()
+    sp = int(s.cuda_stream)
+    assert B.sbox_walsh_nl(t.data_ptr(), 10, 9, mx.data_ptr(), nl.data_ptr(), sp) == B.SBOX_ERR_WORKSPACE
+    assert "sbox_scratch_reserve" in B.last_error()
     torch.cuda.synchronize()
+    assert int(nl.item()) == -5  # nothing was enqueued
+    assert B.sbox_scratch_reserve(8, 9, sp) == B.SBOX_OK
+    assert B.sbox_walsh_nl(t.data_ptr(), 10, 9, mx.data_ptr(), nl.data_ptr(), sp) == B.SBOX_ERR_WORKSPACE
+    assert B.sbox_scratch_reserve(12, 12, sp) == B.SBOX_OK
+    assert B.sbox_scratch_reserve(4, 4, sp) == B.SBOX_OK  # keeps the larger buffer
+    st = B.sbox_walsh_nl(t.data_ptr(), 10, 9, mx.data_ptr(), nl.data_ptr(), sp)
+    assert st == B.SBOX_OK, B.last_error()
+    s.synchronize()
     onl, omx = oracle.walsh_nl(S, 10, 9)
     assert int(nl.item()) == onl and np.array_equal(mx.cpu().numpy(), omx)
+    assert B.sbox_scratch_release(sp) == B.SBOX_OK
+    assert B.sbox_scratch_release(sp) == B.SBOX_OK  # no reservation left: no-op
+    assert B.sbox_walsh_nl(t.data_ptr(), 10, 9, mx.data_ptr(), nl.data_ptr(), sp) == B.SBOX_ERR_WORKSPACE
 
 
 def test_element_width_and_high_bits():
