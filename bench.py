@@ -29,10 +29,13 @@ if ROOT not in sys.path:
 # packed 16-bit ops (v_pk_add_u16 ...) do two element-ops per lane-op.
 PEAK_INT32_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 PEAK_PK16_TOPS = 2 * PEAK_INT32_TOPS
-# Matrix cores as a butterfly engine: one v_mfma_f32_16x16x32_f16 (16 cycles
-# per SIMD at the 2.5 PFLOP/s dense fp16 rate) applies half of H_32 to 16
-# rows, the work of 16 x 16 x 5 = 1,280 butterfly add/subs; 1,024 SIMDs at
-# 2.4 GHz give 1.966e14 butterfly ops/s, the fastest unit for this work.
+# Published dense fp16 matrix-core peak of the MI355X (no sparsity).
+PEAK_FP16_MFMA_TFLOPS = 2500.0
+# One v_mfma_f32_16x16x32_f16 is 16 x 16 x 32 multiply-adds (16,384 flops);
+# at the published peak a SIMD retires one every 16 cycles.  Applied as half
+# of H_32 to 16 rows it does the work of 16 x 16 x 5 = 1,280 butterfly
+# add/subs, so the matrix cores run at most 1.966e14 butterfly ops/s.
+MFMA_F16_FLOPS = 16 * 16 * 32 * 2
 PEAK_MFMA_BUTTERFLY_TOPS = 256 * 4 * 2.4e9 / 16 * 1280 / 1e12
 PEAK_HBM_GBS = 8000.0
 
@@ -41,15 +44,17 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=100,
-                    help="untimed steps first (the clocks ramp up over the first ~20 ms of work)")
+    ap.add_argument("--warmup", type=int, default=100, help="untimed steps first")
+    ap.add_argument("--warmup-ms", type=float, default=60.0,
+                    help="keep warming up until this much time has passed (the clocks ramp up over ~20 ms)")
     ap.add_argument("--cpu-sample-masks", type=int, default=32768,
                     help="masks of the 16x16 box the CPU oracle is timed on")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--quick", action="store_true", help="the headline workload only (no batch, no extras)")
     ap.add_argument("--batched", action="store_true", help="time the mixed 4096-box batch (default unless --quick)")
-    ap.add_argument("--serving", action="store_true", help="also run the Poisson serving rate sweep")
-    ap.add_argument("--serving-count", type=int, default=5000, help="requests per rate in the sweep")
+    ap.add_argument("--serving", action="store_true",
+                    help="the full Poisson serving sweep (1k-50k req/s); without it three rates run unless --quick")
+    ap.add_argument("--serving-count", type=int, default=2000, help="requests per rate in the sweep")
     ap.add_argument("--extra", action="store_true",  # default unless --quick
                     help="also time the other workloads (8x8, 20x16, 16x20, 12x12 slice, 16x16 spectrum)")
     ap.add_argument("--variant", type=int, default=0, choices=(0, 1, 2),
@@ -58,6 +63,8 @@ def parse():
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters) and exit")
     ap.add_argument("--batched-only", action="store_true",
                     help="time only the 4096-box batch (for a profiler run), print it as one JSON object and exit")
+    ap.add_argument("--no-plain-loop", action="store_true",
+                    help="with --batched-only: time the graph replays only, not the loop of single-box calls")
     ap.add_argument("--extra-only", default="",
                     help="comma-separated name prefixes: time only those extra workloads (e.g. criteria_16x16, "
                          "for a profiler run), print them as one JSON object and exit")
@@ -67,15 +74,25 @@ def parse():
     return args
 
 
-# The fused 16x16 kernel each butterfly engine launches, and the file holding
-# its rocprofv3 FETCH_SIZE / WRITE_SIZE figures.
-# Arithmetic type: packed int16 butterflies, or fp16 operands with fp32
-# accumulation on the matrix cores (every value is an integer of at most
-# 2^11 in magnitude when it is an fp16 operand, so both are exact).
-# The roofline peak of each engine is the fastest unit it runs its butterflies
-# on: the packed 16-bit VALU, or the matrix cores.
-KERNELS = {1: ("k_walsh<16,8,0>", "k_walsh_16x16_traffic.json", "i16", PEAK_PK16_TOPS),
-           2: ("k_walsh_mfma16<4>", "k_walsh_mfma16_16x16_traffic.json", "f16", PEAK_MFMA_BUTTERFLY_TOPS)}
+# The fused 16x16 kernel each butterfly engine launches, the file holding its
+# rocprofv3 FETCH_SIZE / WRITE_SIZE figures, the arithmetic type and the
+# roofline it is reported against.  Packed int16 butterflies run on the VALU
+# (peak: packed 16-bit lane-ops); the matrix-core engine keeps every fp16
+# operand an integer of at most 2^11 in magnitude and accumulates in fp32, so
+# it is exact, and its peak is the published dense fp16 matrix-core rate.
+# "mfma_per_mask" is the number of v_mfma_f32_16x16x32_f16 one mask issues.
+KERNELS = {1: {"kernel": "k_walsh<16,8,0>", "traffic": "k_walsh_16x16_traffic.json", "dtype": "i16",
+               "bound": "alu", "peak": PEAK_PK16_TOPS, "unit": "TOP/s", "mfma_per_mask": 0},
+           2: {"kernel": "k_walsh_mfma16<4>", "traffic": "k_walsh_mfma16_16x16_traffic.json", "dtype": "f16",
+               "bound": "mfma", "peak": PEAK_FP16_MFMA_TFLOPS, "unit": "TFLOP/s", "mfma_per_mask": 512}}
+# The paper's own figures (Table 4, Fig. ch2; one Core i7 of 12 threads, 16 GB
+# DDR4, Windows 10, MSVC 2017, Table 3), quoted as context only.
+PAPER_CONTEXT = {
+    "hardware": "Intel Core i7 8400K, 12 threads (as printed), 16 GB DDR4, Windows 10 x64, MSVC 2017 (Table 3)",
+    "walsh_speedup_16x16": 39.784, "nl_speedup_16x16": 563.05,
+    "fwht_16x16_ms": {"primary": 2496726, "a_transposed": 326331, "b_10_threads": 62756, "c_fused_nl": 83013},
+    "nl_16x16_ms": {"primary": 46741627, "a_transposed": 539120, "b_10_threads": 539120, "c_fused_nl": 83015},
+}
 DEFAULT_VARIANT = 2
 # Where each kernel's source starts and which function ends it: the counters
 # stay valid while the shared definitions before the first kernel and this
@@ -132,25 +149,28 @@ def host_cpu_model() -> str:
     return "unknown"
 
 
-def cpu_baseline(S, n, m, sample_masks):
+def cpu_baseline(S, n, m, sample_masks, runs=3):
     """The oracle on the host: all usable cores (threads over masks, the
-    paper's partition of the masks among threads), then one core on a
-    sixteenth of the sample."""
+    paper's partition of the masks among threads), the median of `runs`
+    runs, then one core on a sixteenth of the sample."""
     import numpy as np
     import oracle
     cores = host_cores()
     masks = np.arange(1, min(sample_masks, (1 << m) - 1) + 1, dtype=np.uint32)
     oracle.maxabs_for_masks(S, n, m, masks[:64], nthreads=cores)  # load + warm
-    t0 = time.perf_counter()
-    oracle.maxabs_for_masks(S, n, m, masks, nthreads=cores)
-    dt = time.perf_counter() - t0
+    times = []
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        oracle.maxabs_for_masks(S, n, m, masks, nthreads=cores)
+        times.append(time.perf_counter() - t0)
+    dt = sorted(times)[len(times) // 2]
     one = masks[:max(1, masks.size // 16)]
     t0 = time.perf_counter()
     oracle.maxabs_for_masks(S, n, m, one, nthreads=1)
     dt1 = time.perf_counter() - t0
     return {"value": masks.size * (1 << n) / dt, "unit": "coeff/s", "cores": cores, "kind": "oracle",
-            "sample": "masks b=1..%d of the same %dx%d box (%.1f s wall on %d threads)"
-                      % (masks.size, n, m, dt, cores),
+            "sample": "masks b=1..%d of the same %dx%d box, median of %d runs (%s s wall on %d threads)"
+                      % (masks.size, n, m, runs, ", ".join("%.2f" % t for t in times), cores),
             "single_core": {"value": one.size * (1 << n) / dt1, "unit": "coeff/s",
                             "sample": "masks b=1..%d on 1 thread (%.1f s wall)" % (one.size, dt1)},
             "cpu_model": host_cpu_model()}
@@ -175,7 +195,8 @@ def main():
     if args.batched_only:
         dev = torch.device("cuda:0")
         torch.cuda.set_device(dev)
-        print(json.dumps({"batched": bench_batched(torch, B, inputs, dev)}), flush=True)
+        print(json.dumps({"batched": bench_batched(torch, B, inputs, dev, plain_loop=not args.no_plain_loop)}),
+              flush=True)
         return
     if args.extra_only:
         dev = torch.device("cuda:0")
@@ -197,7 +218,7 @@ def main():
 
     tuning = B.sbox_tuning(0, 0, 0, args.variant) if args.variant else None
     variant = args.variant or DEFAULT_VARIANT
-    kname, tfile, dtype, peak = KERNELS[variant]
+    kinfo = KERNELS[variant]
 
     def step():
         st = B.sbox_walsh_nl_ex(S.data_ptr(), n, m, 2, mx.data_ptr(), nl.data_ptr(), 0, 0,
@@ -205,9 +226,15 @@ def main():
         if st != 0:
             raise RuntimeError(B.last_error())
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize(dev)
+    # untimed warm-up: the requested steps, continued until at least
+    # --warmup-ms of work has run (the clocks ramp up over the first ~20 ms)
+    t_w = time.perf_counter()
+    done = 0
+    while done < args.warmup or (time.perf_counter() - t_w) * 1e3 < args.warmup_ms:
+        for _ in range(10):
+            step()
+        done += 10
+        torch.cuda.synchronize(dev)
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(args.steps)]
     torch.cuda.synchronize(dev)
@@ -223,9 +250,21 @@ def main():
     ev_ms = sorted(a.elapsed_time(b) for a, b in ev)
     ev_mean = sum(ev_ms) / len(ev_ms)
     coeffs = (1 << n) * ((1 << m) - 1)
-    ops = n * coeffs
+    ops = n * coeffs  # Table 1: n add/sub per coefficient
     value = coeffs / (ms_per_step * 1e-3)
     achieved_tops = ops / (ev_mean * 1e-3) / 1e12
+    masks = (1 << m) - 1
+    roof = {"bound": kinfo["bound"], "achieved": achieved_tops, "peak": kinfo["peak"], "unit": kinfo["unit"],
+            "frac": achieved_tops / kinfo["peak"], "traffic": measured_traffic(kinfo["traffic"], variant),
+            "kernel": kinfo["kernel"], "event_ms_per_step": ev_mean,
+            "achieved_is": "algorithmic add/sub of the transform (n per coefficient) per second",
+            "int32_valu_peak": PEAK_INT32_TOPS, "int32_valu_frac": achieved_tops / PEAK_INT32_TOPS,
+            "pk16_valu_peak": PEAK_PK16_TOPS, "pk16_valu_frac": achieved_tops / PEAK_PK16_TOPS}
+    if kinfo["mfma_per_mask"]:
+        issued = kinfo["mfma_per_mask"] * MFMA_F16_FLOPS * masks / (ev_mean * 1e-3) / 1e12
+        roof.update({"mfma_issued_tflops": issued, "mfma_issued_frac": issued / PEAK_FP16_MFMA_TFLOPS,
+                     "mfma_butterfly_peak": PEAK_MFMA_BUTTERFLY_TOPS,
+                     "mfma_butterfly_frac": achieved_tops / PEAK_MFMA_BUTTERFLY_TOPS})
 
     out = {
         "metric": "Walsh coefficients/s, fused NL of a 16x16 S-box (65,535 masks x 65,536-point FWHT)",
@@ -233,33 +272,28 @@ def main():
         "unit": "coeff/s",
         "n_gpus": 1,
         "steps": args.steps,
-        "warmup": args.warmup,
+        "warmup": done,
         "ms_per_step": ms_per_step,
         "higher_is_better": True,
         "scaling": "strong",
         "vs_baseline": None,
-        "dtype": dtype,
+        "dtype": kinfo["dtype"],
         "data": "synthetic",
         "config": {"workload": "single 16x16 S-box, seeded Fisher-Yates permutation (seed %d), fused "
                                "max|W| per mask + NL, no spectrum" % (inputs.SEED_BASE + 2),
-                   "n": n, "m": m, "masks": (1 << m) - 1, "nl": nl_val},
-        # achieved: n add/subs per coefficient over the HIP-event time of the
-        # step (the fused kernel is ~99 % of it; bit-slicing and init the rest)
-        "roofline": {"bound": "alu", "achieved": achieved_tops, "peak": peak, "unit": "TOP/s",
-                     "frac": achieved_tops / peak, "traffic": measured_traffic(tfile, variant),
-                     "kernel": kname, "event_ms_per_step": ev_mean,
-                     "int32_valu_peak": PEAK_INT32_TOPS,
-                     "int32_valu_frac": achieved_tops / PEAK_INT32_TOPS,
-                     "pk16_valu_peak": PEAK_PK16_TOPS,
-                     "pk16_valu_frac": achieved_tops / PEAK_PK16_TOPS},
+                   "n": n, "m": m, "masks": masks, "nl": nl_val},
+        "roofline": roof,
+        "paper_context": dict(PAPER_CONTEXT, speedup_vs_paper_best_fused_nl=PAPER_CONTEXT["nl_16x16_ms"]["c_fused_nl"]
+                              / ms_per_step),
     }
     if args.batched:
         out["batched"] = bench_batched(torch, B, inputs, dev)
     if args.extra:
         out["extra"] = bench_extra(torch, B, inputs, dev)
-    if args.serving:
+    if args.serving or not args.quick:
         from paper_1912_03732_amd import serving
-        out["serving"] = serving.sweep(count=args.serving_count)
+        rates = (1000, 2000, 5000, 10000, 20000, 50000) if args.serving else (2000, 10000, 30000)
+        out["serving"] = serving.sweep(rates=rates, count=args.serving_count)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(S_host, n, m, args.cpu_sample_masks)
     print(json.dumps(out), flush=True)
@@ -323,9 +357,17 @@ def bench_extra(torch, B, inputs, dev, only=()):
             row["roofline"] = {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                                "frac": gbs / PEAK_HBM_GBS}
         else:
-            peak = PEAK_MFMA_BUTTERFLY_TOPS if n in (12, 16) else PEAK_PK16_TOPS
+            # n = 12, 16: the matrix-core engines (published dense fp16 peak);
+            # other n: packed 16-bit VALU butterflies (the last stages of
+            # n > 16 run in int32; the packed peak is the stricter one)
             tops = n * coeffs / (ms * 1e-3) / 1e12
-            row["roofline"] = {"bound": "alu", "achieved": tops, "peak": peak, "unit": "TOP/s", "frac": tops / peak}
+            if n in (12, 16):
+                row["roofline"] = {"bound": "mfma", "achieved": tops, "peak": PEAK_FP16_MFMA_TFLOPS,
+                                   "unit": "TFLOP/s", "frac": tops / PEAK_FP16_MFMA_TFLOPS,
+                                   "mfma_butterfly_frac": tops / PEAK_MFMA_BUTTERFLY_TOPS}
+            else:
+                row["roofline"] = {"bound": "alu", "achieved": tops, "peak": PEAK_PK16_TOPS, "unit": "TOP/s",
+                                   "frac": tops / PEAK_PK16_TOPS}
         return row
 
     w8 = inputs.workload_8x8()
@@ -411,7 +453,7 @@ def bench_extra(torch, B, inputs, dev, only=()):
     return out
 
 
-def bench_batched(torch, B, inputs, dev, reps=5):
+def bench_batched(torch, B, inputs, dev, reps=5, plain_loop=True):
     """4096 mixed boxes (n = m in {6,8,10,12}): one planned batched launch vs a
     loop of single-box calls on one stream."""
     batch = inputs.workload_batched()
@@ -431,6 +473,11 @@ def bench_batched(torch, B, inputs, dev, reps=5):
         g.replay()
     torch.cuda.synchronize(dev)
     t_batch = (time.perf_counter() - t0) / reps
+    coeffs = sum((1 << n) * ((1 << n) - 1) for n in ns)
+    if not plain_loop:
+        plan.close()
+        return {"boxes": len(batch), "sboxes_per_s": len(batch) / t_batch, "ms": t_batch * 1e3,
+                "coeff_per_s": coeffs / t_batch}
     # plain loop: one sbox_walsh_nl_ex per box
     nl = torch.empty(1, dtype=torch.int32, device=dev)
     outs = [torch.empty(1 << n, dtype=torch.int32, device=dev) for n in ns]
@@ -447,7 +494,6 @@ def bench_batched(torch, B, inputs, dev, reps=5):
     loop()
     torch.cuda.synchronize(dev)
     t_loop = time.perf_counter() - t0
-    coeffs = sum((1 << n) * ((1 << n) - 1) for n in ns)
     plan.close()
     return {"boxes": len(batch), "sboxes_per_s": len(batch) / t_batch, "ms": t_batch * 1e3,
             "coeff_per_s": coeffs / t_batch, "plain_loop_ms": t_loop * 1e3,
