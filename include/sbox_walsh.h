@@ -80,9 +80,12 @@ typedef enum {
  *   variant : butterfly engine for the n = 12 and n = 16 fused maximum (no
  *             spectrum): 0 the library's choice (currently 2), 1 packed
  *             16-bit VALU butterflies, 2 matrix cores (fp16 MFMA Hadamard
- *             blocks, exact; split_p does not apply); other sizes and modes
- *             accept 0 or 1 only.  Batched launches and plans apply it to
- *             their n = 12 and n = 16 boxes.
+ *             blocks after popcount stages, exact; split_p does not apply),
+ *             3 (n = 16 only) three matrix-core passes, the first on fp4
+ *             operands taken straight from the table's bits, then two on
+ *             fp16 (exact); other sizes and modes accept 0 or 1 only.
+ *             Batched launches and plans apply it to their n = 12 and
+ *             n = 16 boxes (variant 3 runs n = 12 boxes as variant 2).
  */
 typedef struct sbox_tuning {
     int32_t split_p;

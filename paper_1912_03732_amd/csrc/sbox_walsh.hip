@@ -217,12 +217,13 @@ constexpr int kDefaultVariant = 2;
 #endif
 constexpr int kMfmaRounds = SBW_MFMA_ROUNDS;
 bool mfma_n(int n) { return n == 12 || n == 16; }
-bool use_mfma(int n, const sbox_tuning* tun) {
-  if (!mfma_n(n)) return false;
-  const int v = (tun && tun->variant) ? tun->variant : kDefaultVariant;
-  return v == 2;
+int variant_of(const sbox_tuning* tun) { return (tun && tun->variant) ? tun->variant : kDefaultVariant; }
+bool use_mfma(int n, const sbox_tuning* tun) { return mfma_n(n) && variant_of(tun) >= 2; }
+// n = 16: variant 2 = fp16 passes after popcount stages, 3 = fp4 + fp16 passes
+KFn mfma_kernel(int n, const sbox_tuning* tun) {
+  if (n == 12) return &k_walsh_mfma12;
+  return variant_of(tun) == 3 ? &k_walsh_mx16 : &k_walsh_mfma16<kMfmaRounds>;
 }
-KFn mfma_kernel(int n) { return n == 16 ? &k_walsh_mfma16<kMfmaRounds> : &k_walsh_mfma12; }
 // masks a workgroup works on at once (thread groups per item slot)
 int mfma_groups(int n) { return n == 16 ? 1 : kWG / 64; }
 
@@ -412,7 +413,7 @@ sbox_status run_single(const void* S, int n, int m, int eb, int32_t* maxabs, int
   }
 
   if (layout == 0 && !hist && use_mfma(n, tun)) {
-    const void* fn = (const void*)mfma_kernel(n);
+    const void* fn = (const void*)mfma_kernel(n, tun);
     int occ = 1;
     s = occupancy(fn, &occ);
     if (s) return s;
@@ -616,7 +617,7 @@ sbox_status plan_batch(const sbox_job* jobs, int count, const sbox_tuning* tun, 
     const int p = (tun && tun->split_p && n > 8) ? tun->split_p : default_split(n);
     if (n > 8 && !split_valid(n, p)) return fail(SBOX_ERR_INVALID_ARG, "split_p=%d invalid for n=%d", p, n);
     const bool mc = layout == 0 && use_mfma(n, tun);
-    c.fn = mc ? mfma_kernel(n) : lookup_kernel(n, p, mode_of(base_layout(layout)));
+    c.fn = mc ? mfma_kernel(n, tun) : lookup_kernel(n, p, mode_of(base_layout(layout)));
     if (!c.fn) return fail(SBOX_ERR_INVALID_ARG, "no kernel for n=%d split_p=%d layout=%d", n, p, layout);
     int occ = 1;
     s = occupancy((const void*)c.fn, &occ);
@@ -680,7 +681,17 @@ void bind_batch(BatchLayout& L, void* ws) {
   for (size_t k = 0; k < L.descs.size(); ++k) L.descs[k].F = reinterpret_cast<const uint32_t*>(fbase + L.f_off[k]);
 }
 
-sbox_status launch_batch(const BatchLayout& L, void* ws, hipStream_t st) {
+// Streams and events a plan owns so that its size classes run side by side:
+// class 0 (the largest n, launched first) stays on the caller's stream, class
+// c >= 1 runs on side[c - 1] after `fork` and is joined back through
+// join[c - 1].  Streams keep the default priority.
+struct ClassStreams {
+  std::vector<hipStream_t> side;
+  std::vector<hipEvent_t> join;
+  hipEvent_t fork = nullptr;
+};
+
+sbox_status launch_batch(const BatchLayout& L, void* ws, hipStream_t st, const ClassStreams* cs = nullptr) {
   if (L.count == 0) return SBOX_OK;
   int* queue = reinterpret_cast<int*>(ws);
   const JobDesc* dtab = reinterpret_cast<const JobDesc*>(reinterpret_cast<char*>(ws) + kQueueBytes);
@@ -713,6 +724,8 @@ sbox_status launch_batch(const BatchLayout& L, void* ws, hipStream_t st) {
     s = launch((const void*)&k_zero, dim3(1), dim3(256), args, st);
     if (s) return s;
   }
+  const bool fork = cs && L.classes.size() > 1 && cs->side.size() + 1 >= L.classes.size();
+  if (fork) HIP_TRY(hipEventRecord(cs->fork, st));
   int ci = 0;
   for (const ClassLaunch& c : L.classes) {
     KParams kp{};
@@ -722,8 +735,17 @@ sbox_status launch_batch(const BatchLayout& L, void* ws, hipStream_t st) {
     kp.queue = queue + ci;
     kp.total_items = c.total_items;
     void* args[] = {&kp};
-    s = launch((const void*)c.fn, dim3(c.grid), dim3(kWG), args, st);
+    hipStream_t cst = st;
+    if (fork && ci > 0) {
+      cst = cs->side[ci - 1];
+      HIP_TRY(hipStreamWaitEvent(cst, cs->fork, 0));
+    }
+    s = launch((const void*)c.fn, dim3(c.grid), dim3(kWG), args, cst);
     if (s) return s;
+    if (fork && ci > 0) {
+      HIP_TRY(hipEventRecord(cs->join[ci - 1], cst));
+      HIP_TRY(hipStreamWaitEvent(st, cs->join[ci - 1], 0));
+    }
     ++ci;
   }
   return SBOX_OK;
@@ -850,10 +872,12 @@ sbox_status sbox_walsh_nl_ex(const void* S, int n, int m, int s_elem_bytes, int3
   if (tuning) {
     if (tuning->chunk < 0 || tuning->grid < 0 || tuning->split_p < 0)
       return fail(SBOX_ERR_INVALID_ARG, "negative tuning field");
-    if (tuning->variant < 0 || tuning->variant > 2)
-      return fail(SBOX_ERR_INVALID_ARG, "tuning variant %d (0, 1 or 2)", tuning->variant);
+    if (tuning->variant < 0 || tuning->variant > 3)
+      return fail(SBOX_ERR_INVALID_ARG, "tuning variant %d (0, 1, 2 or 3)", tuning->variant);
     if (tuning->variant == 2 && !(mfma_n(n) && layout == 0))
       return fail(SBOX_ERR_INVALID_ARG, "the matrix-core variant covers n = 12 and 16 without a spectrum only");
+    if (tuning->variant == 3 && !(n == 16 && layout == 0))
+      return fail(SBOX_ERR_INVALID_ARG, "the fp4 matrix-core variant covers n = 16 without a spectrum only");
     if (tuning->split_p && n > 8 && n <= 16 && !split_valid(n, tuning->split_p))
       return fail(SBOX_ERR_INVALID_ARG, "split_p=%d invalid for n=%d", tuning->split_p, n);
     if (tuning->split_p && n <= 16 && n > 8 && layout != 0 && tuning->split_p != default_split(n))
@@ -1201,15 +1225,40 @@ sbox_status sbox_criteria(const void* S, int n, int m, int s_elem_bytes, int32_t
 struct sbox_plan {
   BatchLayout layout;
   void* dev = nullptr;
+  ClassStreams cs;
 };
+
+namespace {
+void release_streams(ClassStreams& cs) {
+  for (hipStream_t s : cs.side) (void)hipStreamDestroy(s);
+  for (hipEvent_t e : cs.join) (void)hipEventDestroy(e);
+  if (cs.fork) (void)hipEventDestroy(cs.fork);
+  cs = ClassStreams{};
+}
+
+// One side stream and join event per size class after the first.
+sbox_status make_streams(size_t classes, ClassStreams* cs) {
+  if (classes < 2) return SBOX_OK;
+  HIP_TRY(hipEventCreateWithFlags(&cs->fork, hipEventDisableTiming));
+  for (size_t i = 1; i < classes; ++i) {
+    hipStream_t s = nullptr;
+    HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    cs->side.push_back(s);
+    hipEvent_t e = nullptr;
+    HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    cs->join.push_back(e);
+  }
+  return SBOX_OK;
+}
+}  // namespace
 
 sbox_status sbox_plan_create(const sbox_job* jobs, int32_t count, const sbox_tuning* tuning, sbox_plan** out) {
   if (!out) return fail(SBOX_ERR_INVALID_ARG, "out is null");
   *out = nullptr;
   if (tuning && (tuning->chunk < 0 || tuning->grid < 0 || tuning->split_p < 0))
     return fail(SBOX_ERR_INVALID_ARG, "negative tuning field");
-  if (tuning && (tuning->variant < 0 || tuning->variant > 2))
-    return fail(SBOX_ERR_INVALID_ARG, "tuning variant %d (0, 1 or 2)", tuning->variant);
+  if (tuning && (tuning->variant < 0 || tuning->variant > 3))
+    return fail(SBOX_ERR_INVALID_ARG, "tuning variant %d (0, 1, 2 or 3)", tuning->variant);
   sbox_plan* p = new sbox_plan();
   sbox_status s = plan_batch(jobs, count, tuning, &p->layout);
   if (s) {
@@ -1230,6 +1279,13 @@ sbox_status sbox_plan_create(const sbox_job* jobs, int32_t count, const sbox_tun
       delete p;
       return fail(SBOX_ERR_HIP, "hipMemcpy: %s", hipGetErrorString(e));
     }
+    s = make_streams(p->layout.classes.size(), &p->cs);
+    if (s) {
+      release_streams(p->cs);
+      (void)hipFree(p->dev);
+      delete p;
+      return s;
+    }
   }
   *out = p;
   return SBOX_OK;
@@ -1237,7 +1293,7 @@ sbox_status sbox_plan_create(const sbox_job* jobs, int32_t count, const sbox_tun
 
 sbox_status sbox_plan_launch(const sbox_plan* plan, void* stream) {
   if (!plan) return fail(SBOX_ERR_INVALID_ARG, "plan is null");
-  return launch_batch(plan->layout, plan->dev, reinterpret_cast<hipStream_t>(stream));
+  return launch_batch(plan->layout, plan->dev, reinterpret_cast<hipStream_t>(stream), &plan->cs);
 }
 
 void sbox_plan_destroy(sbox_plan* plan) {
@@ -1246,6 +1302,7 @@ void sbox_plan_destroy(sbox_plan* plan) {
     (void)hipDeviceSynchronize();
     (void)hipFree(plan->dev);
   }
+  release_streams(plan->cs);
   delete plan;
 }
 

@@ -833,6 +833,233 @@ __global__ __launch_bounds__(kWG, ROUNDS) void k_walsh_mfma16(const KParams kp) 
 }
 
 // ---------------------------------------------------------------------------
+// n = 16, max mode, three matrix-core passes and no popcount stages: the
+// first on fp4 (e2m1) operands taken straight from the bit-sliced words,
+// the other two on fp16.
+//
+// Bits of x as in k_walsh_mfma16: x0..x4 inside a word, x5..x7 index a
+// thread's 8 words, x8..x13 the lane, x14, x15 the wave.  A component value
+// is carried as its bit: (-1)^bit = 1 - 2 bit, so with T the transform of
+// the bits, W = 2^16 [a = 0] - 2 T, and the kernel tracks
+// V = T - 2^15 [a = 0] = -W / 2.
+//   1. Pass 1, v_mfma_scale_f32_16x16x128_f8f6f4 on e2m1: a word ANDed with
+//      0x11111111 << t keeps bit t of every nibble (t = x0 + 2 x1, the
+//      nibble = x2..x4), whose e2m1 value is 0.5, 1 or 2 for t = 0, 1, 2
+//      (bit 3 is the sign, so t = 3 is first shifted down to 2); the
+//      operand's power-of-two scale (2^1, 2^0, 2^-1) makes every kept bit
+//      1.0.  K slots (x2, x3, x4 | x5, x6 | x12, x13), rows x8..x11, eight
+//      16-column blocks of H_128.  Column 0 of block 0 gets -64 as the
+//      accumulator input: the 2^9 tiles that reach output 0 remove 2^15.
+//      |value| <= 64.
+//   2. Pass 2, v_mfma_f32_16x16x32_f16: for a column block and a pair of
+//      tile rows (x8, x9) the 8 pass-1 results over (t, x7) form the
+//      operand's registers (t) and halves (x7); the lane's K slots are tile
+//      rows x10, x11.  |value| <= 2048 (exact in fp16).
+//   3. Exchange through LDS: a lane's upper two bits (pass-1 output bits
+//      2, 3) trade places with the wave (x14, x15).
+//   4. Pass 3, v_mfma_f32_16x16x32_f16 with K slots (pass-2 row bit 0 |
+//      x8, x9 | x14, x15) against H_16 (x) I_2: the first slot is passed
+//      through, the other four bits are transformed.  |value| <= 2^15.
+//   5. The maximum of |V| with abs modifiers.
+// Every bit of x is transformed once (7 + 5 + 4).  Rounds: the eight
+// column blocks of pass 1 two at a time, each pair carried through passes
+// 2 and 3, so one exchange holds a quarter of a mask (double-buffered).
+// ---------------------------------------------------------------------------
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+
+constexpr int kMxSlotWords = 36;                       // 32 registers + 4 words of padding per lane
+constexpr int kMxBufWords = kWG * kMxSlotWords;        // one exchange buffer
+
+__device__ __forceinline__ uint32_t fp4_sign_word(int kbase, int a) {
+  // e2m1 +1 (0x2) or -1 (0xA) for the 8 nibbles k = kbase + nib against output a
+  uint32_t w = 0;
+#pragma unroll
+  for (int nib = 0; nib < 8; ++nib) w |= ((__builtin_popcount((kbase + nib) & a) & 1) ? 0xAu : 0x2u) << (4 * nib);
+  return w;
+}
+
+__global__ __launch_bounds__(kWG, 2) void k_walsh_mx16(const KParams kp) {
+  constexpr int NW = 8;
+  __shared__ __attribute__((aligned(16))) uint32_t lds[2 * kMxBufWords];
+  __shared__ int red[64 * 4];  // per mask of a run of 64: the 4 wave maxima
+  __shared__ long long s_item;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int C = kp.chunk;
+  const int col = lane & 15, g = lane >> 4;
+
+  // Pass-1 B operands: block cb, register p, nibble: K slot
+  // k = nib + 8 p + 32 g against output 16 cb + col.
+  uint32_t B1[8][4];
+#pragma unroll
+  for (int cb = 0; cb < 8; ++cb)
+#pragma unroll
+    for (int p = 0; p < 4; ++p) B1[cb][p] = fp4_sign_word(8 * p + 32 * g, 16 * cb + col);
+  // Pass-2 B operands: the two 16-column halves of H_32, slot kappa = j + 8 g.
+  f16x8 hb0, hb1;
+  // Pass-3 B operands: slot j = h + 2 p3 (h passed through) + 8 g; MFMA hf keeps h = hf.
+  f16x8 hc0, hc1;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int kappa = j + 8 * g;
+    hb0[j] = hsign(kappa & col);
+    hb1[j] = hsign(kappa & (col + 16));
+    const int k4 = (j >> 1) | (g << 2);  // the four transformed bits (x8, x9, x14, x15)
+    hc0[j] = (j & 1) ? (_Float16)0.0f : hsign(k4 & col);
+    hc1[j] = (j & 1) ? hsign(k4 & col) : (_Float16)0.0f;
+  }
+  const float fix = col == 0 ? -64.0f : 0.0f;
+  const f32x4 cfix = {fix, fix, fix, fix};
+  const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+  // exchange slots: written as (lane >> 4, wave, lane & 15), read with the
+  // wave and the lane's upper bits swapped
+  const int wslot = ((g * 4 + wave) * 16 + col) * kMxSlotWords;
+  const int rslot = ((wave * 4 + g) * 16 + col) * kMxSlotWords;
+
+  for (;;) {
+    if (tid == 0) s_item = (long long)atomicAdd(kp.queue, 1);
+    __syncthreads();
+    const long long item = __builtin_amdgcn_readfirstlane((int)s_item);
+    __syncthreads();
+    if (item >= kp.total_items) break;
+    JobDesc jd;
+    long long li;
+    if (kp.jobs == nullptr) {
+      jd = kp.job0;
+      li = item;
+    } else {  // batched: find the job owning this item
+      int lo = 0, hi = kp.njobs - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (kp.jobs[mid].item_begin <= item) lo = mid; else hi = mid - 1;
+      }
+      jd = kp.jobs[lo];
+      li = item - jd.item_begin;
+    }
+    const long long kfirst = li * (long long)C;
+    const long long kend = 1LL << jd.m;
+    const long long wb = (long long)tid * NW;
+    const int n = jd.n;
+    int runmin = 0x7fffffff;
+    uint32_t G[NW], Fn[NW];
+
+    for (int step = 0; step < C; ++step) {
+      const long long k = kfirst + step;
+      const bool inrange = k < kend;
+      if (step == 0) {
+#pragma unroll
+        for (int w = 0; w < NW; ++w) G[w] = 0;
+        if (inrange) {
+          const long long gk = gray(k);
+          for (int i = 0; i < jd.m; ++i)
+            if ((gk >> i) & 1) load_words<NW>(G, jd.F + (long long)i * jd.nwords + wb, true);
+        }
+      } else if (inrange) {
+#pragma unroll
+        for (int w = 0; w < NW; ++w) G[w] ^= Fn[w];
+      }
+      if (step + 1 < C && k + 1 < kend) {
+        const int i = __builtin_ctzll((unsigned long long)(k + 1));
+        load_words<NW>(Fn, jd.F + (long long)i * jd.nwords + wb, false);
+      }
+      // pass-1 operands: A[t][x7] register p = bit t of every nibble of word 4 x7 + p
+      i32x8 A[4][2];
+#pragma unroll
+      for (int x7 = 0; x7 < 2; ++x7)
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+          const uint32_t w = G[4 * x7 + p];
+          A[0][x7][p] = (int)(w & 0x11111111u);
+          A[1][x7][p] = (int)(w & 0x22222222u);
+          A[2][x7][p] = (int)(w & 0x44444444u);
+          A[3][x7][p] = (int)((w >> 1) & 0x44444444u);
+          A[0][x7][p + 4] = 0;
+          A[1][x7][p + 4] = 0;
+          A[2][x7][p + 4] = 0;
+          A[3][x7][p + 4] = 0;
+        }
+      float m0 = 0.0f, m1 = 0.0f;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        uint32_t* buf = lds + (r & 1) * kMxBufWords;
+        // ---- pass 1 for column blocks 2r, 2r + 1, cast, pass 2
+        uint32_t X[2][2][2][4];  // [block][hf2][s][x8 x9]: pass-2 results as fp16 pairs (pass-3 operands)
+#pragma unroll
+        for (int cl = 0; cl < 2; ++cl) {
+          const int cb = 2 * r + cl;
+          const i32x8 b = {(int)B1[cb][0], (int)B1[cb][1], (int)B1[cb][2], (int)B1[cb][3], 0, 0, 0, 0};
+          f32x4 D[4][2];
+#pragma unroll
+          for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int x7 = 0; x7 < 2; ++x7)
+              D[t][x7] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
+                  A[t][x7], b, cb == 0 ? cfix : zero, 4, 4, 0, t == 0 ? 128 : (t == 1 ? 127 : 126), 0, 127);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {  // tile row pair (x8, x9)
+            const f16x8 av = as_f16x8(pk_cvt_f16(D[0][0][i], D[0][1][i]), pk_cvt_f16(D[1][0][i], D[1][1][i]),
+                                      pk_cvt_f16(D[2][0][i], D[2][1][i]), pk_cvt_f16(D[3][0][i], D[3][1][i]));
+            const f32x4 e0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(av, hb0, zero, 0, 0, 0);
+            const f32x4 e1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(av, hb1, zero, 0, 0, 0);
+            X[cl][0][0][i] = pk_cvt_f16(e0[0], e0[1]);
+            X[cl][0][1][i] = pk_cvt_f16(e0[2], e0[3]);
+            X[cl][1][0][i] = pk_cvt_f16(e1[0], e1[1]);
+            X[cl][1][1][i] = pk_cvt_f16(e1[2], e1[3]);
+          }
+        }
+        // ---- exchange (double-buffered: one barrier per round)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int cl = q >> 2, hf = (q >> 1) & 1, s = q & 1;
+          *reinterpret_cast<uint4*>(buf + wslot + 4 * q) =
+              uint4{X[cl][hf][s][0], X[cl][hf][s][1], X[cl][hf][s][2], X[cl][hf][s][3]};
+        }
+        __syncthreads();
+        uint32_t Y[8][4];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const uint4 v = *reinterpret_cast<const uint4*>(buf + rslot + 4 * q);
+          Y[q][0] = v.x; Y[q][1] = v.y; Y[q][2] = v.z; Y[q][3] = v.w;
+        }
+        // ---- pass 3 and the maximum
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const f16x8 av = as_f16x8(Y[q][0], Y[q][1], Y[q][2], Y[q][3]);
+          const f32x4 d0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(av, hc0, zero, 0, 0, 0);
+          const f32x4 d1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(av, hc1, zero, 0, 0, 0);
+          m0 = fmaxf(fmaxf(m0, fabsf(d0[0])), fabsf(d1[0]));
+          m1 = fmaxf(fmaxf(m1, fabsf(d0[1])), fabsf(d1[1]));
+          m0 = fmaxf(fmaxf(m0, fabsf(d0[2])), fabsf(d1[2]));
+          m1 = fmaxf(fmaxf(m1, fabsf(d0[3])), fabsf(d1[3]));
+        }
+      }
+      const int mx = wave_max((int)fmaxf(m0, m1));
+      if (lane == 0) red[(step & 63) * 4 + wave] = mx;
+      if ((step & 63) == 63 || step == C - 1) {
+        __syncthreads();
+        if (wave == 0) {
+          const long long s0 = step & ~63LL;
+          const long long kk = kfirst + s0 + lane;
+          int v = 0x7fffffff;
+          if (s0 + lane <= step && kk < kend && kk != 0) {
+            const int* pr = red + lane * 4;
+            const int pm = max(max(pr[0], pr[1]), max(pr[2], pr[3]));
+            if (jd.maxabs) jd.maxabs[(uint32_t)gray(kk)] = 2 * pm;
+            v = (1 << (n - 1)) - pm;
+          }
+#pragma unroll
+          for (int o = 1; o < 64; o <<= 1) v = min(v, __shfl_xor(v, o, 64));
+          runmin = min(runmin, v);
+        }
+      }
+    }
+    if (tid == 0 && runmin != 0x7fffffff) atomicMin(jd.nl, runmin);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // n = 12, max mode, matrix-core variant: one wave per mask, four masks per
 // workgroup, no workgroup barrier inside a mask.
 //

@@ -468,3 +468,54 @@ def test_single_call_graph_replay(n, m, spectrum):
     g.replay()
     torch.cuda.synchronize()
     assert int(nl.item()) == oracle.walsh_nl(new, n, m)[0]
+
+
+@pytest.mark.parametrize("m,kind", [(1, "random"), (4, "random"), (9, "random"), (16, "perm"), (16, "inv"),
+                                    (16, "const"), (16, "affine"), (16, "zero"), (19, "random")])
+def test_fp4_matrix_core_variant_16(m, kind):
+    """n = 16 fused maximum on three matrix-core passes (fp4 then fp16,
+    tuning variant 3), bit-exact; the constant, affine and all-zero boxes
+    reach |W| = 2^16 at a = 0 and elsewhere."""
+    x = np.arange(1 << 16)
+    if kind == "perm":
+        S = inputs.workload_16x16()["perm"]
+    elif kind == "inv":
+        S = inputs.workload_16x16()["inv"]
+    elif kind == "const":
+        S = (inputs.permutation(16, inputs.rng(6001)).astype(np.uint32) & 0x7FFF).astype(np.uint16)
+    elif kind == "affine":
+        S = (x ^ (x << 3) ^ (x >> 2) ^ 0x1234) & 0xFFFF  # GF(2)-affine
+    elif kind == "zero":
+        S = np.zeros(1 << 16, np.uint16)
+    else:
+        S = table(16, m, 15500 + m)
+    nl, mx = check_against_oracle(S, 16, m, nthreads=NT, tuning=B.sbox_tuning(0, 0, 0, 3))
+    if kind == "inv":
+        assert nl == 32512
+    if kind == "const":
+        assert mx[0x8000] == 65536
+    if kind in ("affine", "zero"):
+        assert nl == 0
+
+
+@pytest.mark.parametrize("chunk,grid", [(1, 1), (7, 33), (64, 0), (200, 5)])
+def test_fp4_matrix_core_launch_shapes(chunk, grid):
+    S = table(16, 10, 15600 + chunk)
+    check_against_oracle(S, 16, 10, nthreads=NT, tuning=B.sbox_tuning(0, chunk, grid, 3))
+
+
+def test_fp4_matrix_core_in_a_plan():
+    """Variant 3 inside a batched plan with n = 12 and other boxes."""
+    import torch
+    g = inputs.rng(15700)
+    boxes = [(16, 16, inputs.permutation(16, g)), (16, 5, inputs.random_function(16, 5, g)),
+             (12, 12, inputs.permutation(12, g)), (8, 8, inputs.permutation(8, g))]
+    tabs = [dev_table(S, m) for n, m, S in boxes]
+    plan = B.Plan(tabs, [b[0] for b in boxes], [b[1] for b in boxes], tuning=B.sbox_tuning(0, 0, 0, 3))
+    plan.launch()
+    torch.cuda.synchronize()
+    nl = plan.nl.cpu().numpy()
+    for i, (n, m, S) in enumerate(boxes):
+        onl, omx = oracle.walsh_nl(S, n, m, nthreads=NT)
+        assert nl[i] == onl and np.array_equal(plan.maxabs[i].cpu().numpy(), omx), (i, n, m)
+    plan.close()
