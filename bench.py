@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--cpu-sample-masks", type=int, default=32768,
                     help="masks of the 16x16 box the CPU oracle is timed on")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--paper-cpu-16", action="store_true",
+                    help="also rerun the paper's CPU methods at 16x16 (16 GiB matrices; minutes)")
     ap.add_argument("--quick", action="store_true", help="the headline workload only (no batch, no extras)")
     ap.add_argument("--batched", action="store_true", help="time the mixed 4096-box batch (default unless --quick)")
     ap.add_argument("--serving", action="store_true",
@@ -176,6 +178,49 @@ def cpu_baseline(S, n, m, sample_masks, runs=3):
             "cpu_model": host_cpu_model()}
 
 
+def paper_table4(sizes=((10, 10), (12, 12)), sweep_size=(12, 12), sweep=range(7, 13), threads=10):
+    """The paper's CPU methods (Table 4, Fig. ch1) rerun on this host with the
+    oracle's routines, as a historical baseline:
+      primary: the a-major matrix of Algorithm 1 on one thread, then the
+               unfused NL scan of Algorithm 2;
+      (a)      the transposed (b-major) matrix of Section 5.1, one thread;
+      (b)      (a) with the masks split among `threads` threads (Alg. 4);
+      (c)      (b) with the maximum folded into the transform (Alg. 5), no matrix.
+    'fwht_ms' is the matrix (or fused pass) time, 'nl_ms' the scan after it;
+    the sweep repeats (b) over the paper's 7..12 threads.  Seeded permutations."""
+    import numpy as np
+    import oracle
+    from paper_1912_03732_amd import inputs
+
+    def timed(fn):
+        t0 = time.perf_counter()
+        r = fn()
+        return (time.perf_counter() - t0) * 1e3, r
+
+    out = {}
+    for n, m in sizes:
+        S = inputs.permutation(n, inputs.rng(inputs.SEED_BASE + 10 + n))
+        row = {}
+        for name, layout, nt in (("primary", oracle.A_MAJOR, 1), ("a_transposed", oracle.B_MAJOR, 1),
+                                 ("b_threads", oracle.B_MAJOR, threads)):
+            t_w, W = timed(lambda: oracle.spectrum(S, n, m, layout, nthreads=nt))
+            t_n, (nl, _) = timed(lambda: oracle.nl_from_spectrum(W, n, m, layout, nthreads=nt))
+            row[name] = {"fwht_ms": t_w, "nl_ms": t_n, "nl": nl, "threads": nt}
+            del W
+        t_c, (nl, _) = timed(lambda: oracle.walsh_nl(S, n, m, nthreads=threads))
+        row["c_fused"] = {"fwht_ms": t_c, "nl_ms": t_c, "nl": nl, "threads": threads}
+        out["%dx%d" % (n, m)] = row
+    n, m = sweep_size
+    S = inputs.permutation(n, inputs.rng(inputs.SEED_BASE + 10 + n))
+    sw = {}
+    for nt in sweep:
+        t_w, W = timed(lambda: oracle.spectrum(S, n, m, oracle.B_MAJOR, nthreads=nt))
+        sw[str(nt)] = t_w
+        del W
+    out["thread_sweep_b_%dx%d_fwht_ms" % (n, m)] = sw
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -296,6 +341,9 @@ def main():
         out["serving"] = serving.sweep(rates=rates, count=args.serving_count)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(S_host, n, m, args.cpu_sample_masks)
+        big = ((10, 10), (12, 12), (16, 16)) if args.paper_cpu_16 else ((10, 10), (12, 12))
+        out["cpu_baseline"]["paper_table4"] = paper_table4(
+            sizes=big, sweep_size=(16, 16) if args.paper_cpu_16 else (12, 12))
     print(json.dumps(out), flush=True)
 
 

@@ -52,9 +52,10 @@ def _load():
         lib.oracle_walsh_nl.argtypes = [u32p, ctypes.c_int, ctypes.c_int, i32p, i32p, ctypes.c_int]
         lib.oracle_walsh_maxabs_masks.argtypes = [u32p, ctypes.c_int, ctypes.c_int, u32p,
                                                   ctypes.c_int64, i32p, ctypes.c_int]
-        lib.oracle_spectrum.argtypes = [u32p, ctypes.c_int, ctypes.c_int, ctypes.c_int, i32p]
-        lib.oracle_nl_from_spectrum.argtypes = [i32p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                                i32p, i32p]
+        lib.oracle_spectrum_threads.argtypes = [u32p, ctypes.c_int, ctypes.c_int, ctypes.c_int, i32p,
+                                                ctypes.c_int]
+        lib.oracle_nl_from_spectrum_threads.argtypes = [i32p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                                        i32p, i32p, ctypes.c_int]
         lib.oracle_walsh_column.argtypes = [u32p, ctypes.c_int, ctypes.c_int, ctypes.c_uint32, i32p]
         lib.oracle_walsh_entry.argtypes = [u32p, ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32]
         lib.oracle_walsh_entry.restype = ctypes.c_int32
@@ -71,8 +72,8 @@ def _load():
         lib.oracle_unit_autocorrelation_masks.argtypes = [u32p, ctypes.c_int, ctypes.c_int, u32p, ctypes.c_int64,
                                                           i32p, ctypes.c_int]
         lib.oracle_unit_autocorrelation_masks.restype = ctypes.c_int
-        for f in (lib.oracle_walsh_nl, lib.oracle_walsh_maxabs_masks, lib.oracle_spectrum,
-                  lib.oracle_nl_from_spectrum, lib.oracle_walsh_column):
+        for f in (lib.oracle_walsh_nl, lib.oracle_walsh_maxabs_masks, lib.oracle_spectrum_threads,
+                  lib.oracle_nl_from_spectrum_threads, lib.oracle_walsh_column):
             f.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -115,27 +116,29 @@ def maxabs_for_masks(S, n: int, m: int, masks, nthreads: int = 1) -> np.ndarray:
     return out
 
 
-def spectrum(S, n: int, m: int, layout: int = B_MAJOR) -> np.ndarray:
-    """Full spectrum, shape (2^m, 2^n) for B_MAJOR or (2^n, 2^m) for A_MAJOR."""
+def spectrum(S, n: int, m: int, layout: int = B_MAJOR, nthreads: int = 1) -> np.ndarray:
+    """Full spectrum, shape (2^m, 2^n) for B_MAJOR or (2^n, 2^m) for A_MAJOR
+    (masks split among nthreads threads in contiguous blocks)."""
     lib = _load()
     t = _table(S, n)
     W = np.empty(1 << (n + m), dtype=np.int32)
-    rc = lib.oracle_spectrum(_p(t, ctypes.c_uint32), n, m, int(layout), _p(W, ctypes.c_int32))
+    rc = lib.oracle_spectrum_threads(_p(t, ctypes.c_uint32), n, m, int(layout), _p(W, ctypes.c_int32),
+                                     int(nthreads))
     if rc != 0:
-        raise ValueError("oracle_spectrum rejected its arguments")
+        raise ValueError("oracle_spectrum_threads rejected its arguments")
     return W.reshape((1 << m, 1 << n) if layout == B_MAJOR else (1 << n, 1 << m))
 
 
-def nl_from_spectrum(W, n: int, m: int, layout: int = B_MAJOR):
+def nl_from_spectrum(W, n: int, m: int, layout: int = B_MAJOR, nthreads: int = 1):
     """Unfused re-scan of a stored spectrum.  Returns (nl, maxabs[2^m])."""
     lib = _load()
     w = np.ascontiguousarray(np.asarray(W, dtype=np.int32).reshape(-1))
     maxabs = np.empty(1 << m, dtype=np.int32)
     nl = np.zeros(1, dtype=np.int32)
-    rc = lib.oracle_nl_from_spectrum(_p(w, ctypes.c_int32), n, m, int(layout),
-                                     _p(maxabs, ctypes.c_int32), _p(nl, ctypes.c_int32))
+    rc = lib.oracle_nl_from_spectrum_threads(_p(w, ctypes.c_int32), n, m, int(layout),
+                                             _p(maxabs, ctypes.c_int32), _p(nl, ctypes.c_int32), int(nthreads))
     if rc != 0:
-        raise ValueError("oracle_nl_from_spectrum rejected its arguments")
+        raise ValueError("oracle_nl_from_spectrum_threads rejected its arguments")
     return int(nl[0]), maxabs
 
 

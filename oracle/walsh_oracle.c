@@ -175,40 +175,63 @@ int oracle_walsh_maxabs_masks(const uint32_t* S, int n, int m, const uint32_t* b
 
 /*
  * Full spectrum (all 2^(n+m) coefficients, row b = 0 included) in the
- * requested layout.  W must hold 2^(n+m) int32.
+ * requested layout.  W must hold 2^(n+m) int32.  nthreads <= 1 runs
+ * serially; larger values split the masks into contiguous blocks, one per
+ * thread (the partition of Algorithms 4 and 5), each thread transforming
+ * its own columns with a buffer of its own.
  */
-int oracle_spectrum(const uint32_t* S, int n, int m, int layout, int32_t* W) {
-    if (!S || !W || !valid_nm(n, m) || n + m > 30) return -1;
+int oracle_spectrum_threads(const uint32_t* S, int n, int m, int layout, int32_t* W, int nthreads) {
+    if (!S || !W || !valid_nm(n, m) || n + m > 32) return -1;
     if (layout != ORACLE_B_MAJOR && layout != ORACLE_A_MAJOR) return -1;
     const uint32_t N = 1u << n;
     const uint32_t M = 1u << m;
-    int32_t* f = (int32_t*)malloc(sizeof(int32_t) * N);
-    if (!f) return -1;
-    for (uint32_t b = 0; b < M; ++b) {
-        polarity_column(S, n, b, f);
-        fwht_inplace(f, n);
-        for (uint32_t a = 0; a < N; ++a) {
-            if (layout == ORACLE_B_MAJOR)
-                W[(size_t)b * N + a] = f[a];
-            else
-                W[(size_t)a * M + b] = f[a];
+    int failed = 0;
+    if (nthreads < 1) nthreads = 1;
+#pragma omp parallel num_threads(nthreads) reduction(| : failed)
+    {
+        int32_t* f = (int32_t*)malloc(sizeof(int32_t) * N);
+        if (!f) {
+            failed = 1;
+        } else {
+#pragma omp for schedule(static)
+            for (int64_t bb = 0; bb < (int64_t)M; ++bb) {
+                const uint32_t b = (uint32_t)bb;
+                polarity_column(S, n, b, f);
+                fwht_inplace(f, n);
+                for (uint32_t a = 0; a < N; ++a) {
+                    if (layout == ORACLE_B_MAJOR)
+                        W[(size_t)b * N + a] = f[a];
+                    else
+                        W[(size_t)a * M + b] = f[a];
+                }
+            }
+            free(f);
         }
     }
-    free(f);
-    return 0;
+    return failed ? -1 : 0;
+}
+
+int oracle_spectrum(const uint32_t* S, int n, int m, int layout, int32_t* W) {
+    return oracle_spectrum_threads(S, n, m, layout, W, 1);
 }
 
 /*
  * Unfused path (Algorithm 2, then Algorithm 6): re-scan a stored spectrum
  * for the per-mask maximum and the nonlinearity.  maxabs may be NULL.
+ * nthreads as for oracle_spectrum_threads (each thread scans a contiguous
+ * block of masks).
  */
-int oracle_nl_from_spectrum(const int32_t* W, int n, int m, int layout, int32_t* maxabs, int32_t* nl) {
-    if (!W || !nl || !valid_nm(n, m) || n + m > 30) return -1;
+int oracle_nl_from_spectrum_threads(const int32_t* W, int n, int m, int layout, int32_t* maxabs, int32_t* nl,
+                                    int nthreads) {
+    if (!W || !nl || !valid_nm(n, m) || n + m > 32) return -1;
     if (layout != ORACLE_B_MAJOR && layout != ORACLE_A_MAJOR) return -1;
     const uint32_t N = 1u << n;
     const uint32_t M = 1u << m;
     int32_t best = (int32_t)(N >> 1);
-    for (uint32_t b = 0; b < M; ++b) {
+    if (nthreads < 1) nthreads = 1;
+#pragma omp parallel for num_threads(nthreads) schedule(static) reduction(min : best)
+    for (int64_t bb = 0; bb < (int64_t)M; ++bb) {
+        const uint32_t b = (uint32_t)bb;
         int32_t mx = 0;
         for (uint32_t a = 0; a < N; ++a) {
             const int32_t w = layout == ORACLE_B_MAJOR ? W[(size_t)b * N + a] : W[(size_t)a * M + b];
@@ -222,6 +245,10 @@ int oracle_nl_from_spectrum(const int32_t* W, int n, int m, int layout, int32_t*
     }
     *nl = best;
     return 0;
+}
+
+int oracle_nl_from_spectrum(const int32_t* W, int n, int m, int layout, int32_t* maxabs, int32_t* nl) {
+    return oracle_nl_from_spectrum_threads(W, n, m, layout, maxabs, nl, 1);
 }
 
 /*

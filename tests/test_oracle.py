@@ -186,6 +186,15 @@ def test_threaded_equals_serial():
     masks = np.array([1, 7, 1023, 512, 3])
     assert np.array_equal(oracle.maxabs_for_masks(S, 11, 10, masks, nthreads=3),
                           oracle.walsh_nl(S, 11, 10)[1][masks])
+    # the stored spectrum and its re-scan split over threads (Alg. 4/5's partition)
+    for layout in (oracle.B_MAJOR, oracle.A_MAJOR):
+        W1 = oracle.spectrum(S, 11, 10, layout)
+        W4 = oracle.spectrum(S, 11, 10, layout, nthreads=4)
+        assert np.array_equal(W1, W4)
+        r1 = oracle.nl_from_spectrum(W1, 11, 10, layout)
+        r4 = oracle.nl_from_spectrum(W1, 11, 10, layout, nthreads=5)
+        assert r1[0] == r4[0] and np.array_equal(r1[1], r4[1])
+        assert r1[0] == oracle.walsh_nl(S, 11, 10)[0]
 
 
 @pytest.mark.parametrize("n,m", [(5, 5), (8, 6), (9, 9)])
