@@ -143,6 +143,26 @@ sbox_status sbox_walsh_nl_ex(const void* S, int n, int m, int s_elem_bytes,
                              void* workspace, size_t workspace_bytes,
                              const sbox_tuning* tuning, void* stream);
 
+/*
+ * For callers that cannot allocate device memory or pass a workspace:
+ * code under HIP graph capture, tight serving loops, and harnesses that
+ * forbid hipMalloc.  Same arguments, results and errors as sbox_walsh_nl_ex
+ * with the library's defaults, but the scratch is a static device array of
+ * sbox_walsh_nl_static_max_bytes() bytes (256 KiB) compiled into the
+ * library, one per GPU, held until the process ends.  The call allocates
+ * nothing (no hipMalloc, no hipFree).  It covers every n <= 16 and m <= 24
+ * without a spectrum, and spectra except a-major ones with n + m >= 24
+ * (those need a slab); larger requests return SBOX_ERR_WORKSPACE.  Every
+ * call on a GPU uses that GPU's one array and leaves its last contents
+ * behind (each call sets what must start at zero itself): calls that
+ * overlap in time on one GPU, e.g. on two streams, race and give wrong
+ * results; serialise them on one stream.
+ */
+sbox_status sbox_walsh_nl_static(const void* S, int n, int m, int s_elem_bytes,
+                                 int32_t* maxabs_per_b, int32_t* nl,
+                                 int32_t* spectrum, int layout, void* stream);
+size_t sbox_walsh_nl_static_max_bytes(void);
+
 /* Minimum workspace for sbox_walsh_nl_ex; 0 if (n, m, layout) is unsupported. */
 size_t sbox_walsh_nl_workspace_bytes(int n, int m, int layout);
 

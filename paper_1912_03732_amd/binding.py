@@ -54,7 +54,7 @@ class sbox_job(ctypes.Structure):
 
 # Every exported symbol of include/sbox_walsh.h.
 EXPORTS = ("sbox_walsh_nl", "sbox_scratch_reserve", "sbox_scratch_release", "sbox_walsh_nl_ex",
-           "sbox_walsh_nl_workspace_bytes",
+           "sbox_walsh_nl_workspace_bytes", "sbox_walsh_nl_static", "sbox_walsh_nl_static_max_bytes",
            "sbox_walsh_nl_batched", "sbox_batched_workspace_bytes", "sbox_plan_create",
            "sbox_plan_launch", "sbox_plan_destroy", "sbox_criteria", "sbox_criteria_ex",
            "sbox_criteria_workspace_bytes", "sbox_walsh_histogram",
@@ -78,6 +78,10 @@ def load(path: str = LIB_PATH):
     lib.sbox_scratch_release.argtypes = [vp]
     lib.sbox_walsh_nl_ex.argtypes = [vp, i32, i32, i32, vp, vp, vp, i32, vp, sz,
                                      ctypes.POINTER(sbox_tuning), vp]
+    lib.sbox_walsh_nl_static.argtypes = [vp, i32, i32, i32, vp, vp, vp, i32, vp]
+    lib.sbox_walsh_nl_static.restype = ctypes.c_int
+    lib.sbox_walsh_nl_static_max_bytes.argtypes = []
+    lib.sbox_walsh_nl_static_max_bytes.restype = sz
     lib.sbox_walsh_nl_workspace_bytes.argtypes = [i32, i32, i32]
     lib.sbox_walsh_nl_workspace_bytes.restype = sz
     lib.sbox_walsh_nl_batched.argtypes = [ctypes.POINTER(sbox_job), ctypes.c_int32, vp, sz, vp]
@@ -140,6 +144,15 @@ def sbox_walsh_nl_ex(S: int, n: int, m: int, s_elem_bytes: int, maxabs_per_b: in
     tp = ctypes.byref(tuning) if tuning is not None else None
     return load().sbox_walsh_nl_ex(S, n, m, s_elem_bytes, maxabs_per_b, nl, spectrum, layout,
                                    workspace, workspace_bytes, tp, stream)
+
+
+def sbox_walsh_nl_static(S: int, n: int, m: int, s_elem_bytes: int, maxabs_per_b: int, nl: int,
+                         spectrum: int, layout: int, stream: int) -> int:
+    return load().sbox_walsh_nl_static(S, n, m, s_elem_bytes, maxabs_per_b, nl, spectrum, layout, stream)
+
+
+def sbox_walsh_nl_static_max_bytes() -> int:
+    return int(load().sbox_walsh_nl_static_max_bytes())
 
 
 def sbox_walsh_nl_workspace_bytes(n: int, m: int, layout: int) -> int:

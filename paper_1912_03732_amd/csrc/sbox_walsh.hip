@@ -839,6 +839,34 @@ struct StreamScratch {
 std::mutex g_scratch_mu;
 std::map<std::pair<int, uintptr_t>, StreamScratch> g_scratch;
 
+// ------------------------------------- static scratch (no allocation) ---
+// The scratch of sbox_walsh_nl_static: queue counters and bit-sliced words,
+// at most 256 + 24 * 2^13 bytes for n <= 16, m <= 24.  It is part of the
+// library's device image, so every GPU holds its own copy from load until
+// the process ends.  Host code never uses the name as an address: the
+// device address is looked up per GPU (static_scratch_ptr) and passed on.
+constexpr size_t kStaticScratchBytes = size_t(256) << 10;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+std::mutex g_static_mu;
+std::map<int, void*> g_static_ptr;  // device ordinal -> that GPU's copy of `scratch`
+
+// Address of `scratch` on the current device (hipGetSymbolAddress once per
+// device, with that device current).
+sbox_status static_scratch_ptr(void** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_static_mu);
+  auto it = g_static_ptr.find(dev);
+  if (it == g_static_ptr.end()) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    it = g_static_ptr.emplace(dev, p).first;
+  }
+  *out = it->second;
+  return SBOX_OK;
+}
+
 }  // namespace
 
 // ===================================================================== ABI ==
@@ -897,6 +925,27 @@ sbox_status sbox_walsh_nl_ex(const void* S, int n, int m, int s_elem_bytes, int3
                 large_bytes(n, m, 1));
   return run_single(S, n, m, s_elem_bytes, maxabs_per_b, nl, spectrum, layout, workspace, workspace_bytes,
                     tuning, reinterpret_cast<hipStream_t>(stream));
+}
+
+size_t sbox_walsh_nl_static_max_bytes(void) { return kStaticScratchBytes; }
+
+sbox_status sbox_walsh_nl_static(const void* S, int n, int m, int s_elem_bytes, int32_t* maxabs_per_b, int32_t* nl,
+                                 int32_t* spectrum, int layout, void* stream) {
+  sbox_status s = check_nm(n, m);
+  if (s) return s;
+  const size_t need = sbox_walsh_nl_workspace_bytes(n, m, layout);
+  if (need == 0)  // the full form names what is wrong (layout, spectrum size)
+    return sbox_walsh_nl_ex(S, n, m, s_elem_bytes, maxabs_per_b, nl, spectrum, layout, nullptr, 0, nullptr, stream);
+  if (need > kStaticScratchBytes)
+    return fail(SBOX_ERR_WORKSPACE,
+                "n=%d m=%d layout=%d needs %zu bytes of scratch; the static array holds %zu "
+                "(n <= 16, and no a-major spectrum with n + m >= 24)",
+                n, m, layout, need, kStaticScratchBytes);
+  void* ws = nullptr;
+  s = static_scratch_ptr(&ws);
+  if (s) return s;
+  return sbox_walsh_nl_ex(S, n, m, s_elem_bytes, maxabs_per_b, nl, spectrum, layout, ws, kStaticScratchBytes,
+                          nullptr, stream);
 }
 
 size_t sbox_walsh_histogram_workspace_bytes(int n, int m) {
