@@ -59,8 +59,9 @@ def parse():
     ap.add_argument("--serving-count", type=int, default=2000, help="requests per rate in the sweep")
     ap.add_argument("--extra", action="store_true",  # default unless --quick
                     help="also time the other workloads (8x8, 20x16, 16x20, 12x12 slice, 16x16 spectrum)")
-    ap.add_argument("--variant", type=int, default=0, choices=(0, 1, 2),
-                    help="butterfly engine for the 16x16 kernel: 0 library default, 1 VALU, 2 matrix cores")
+    ap.add_argument("--variant", type=int, default=0, choices=(0, 1, 2, 3),
+                    help="butterfly engine for the 16x16 kernel: 0 library default, 1 VALU, 2 matrix cores "
+                         "after popcount stages, 3 fp4 + fp16 matrix-core passes")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters) and exit")
     ap.add_argument("--batched-only", action="store_true",
@@ -79,14 +80,22 @@ def parse():
 # The fused 16x16 kernel each butterfly engine launches, the file holding its
 # rocprofv3 FETCH_SIZE / WRITE_SIZE figures, the arithmetic type and the
 # roofline it is reported against.  Packed int16 butterflies run on the VALU
-# (peak: packed 16-bit lane-ops); the matrix-core engine keeps every fp16
-# operand an integer of at most 2^11 in magnitude and accumulates in fp32, so
-# it is exact, and its peak is the published dense fp16 matrix-core rate.
-# "mfma_per_mask" is the number of v_mfma_f32_16x16x32_f16 one mask issues.
+# (peak: packed 16-bit lane-ops).  The matrix-core engines are exact (every
+# operand an integer of at most 2^11, or a table bit, fp32 accumulation);
+# their peak is the published dense fp16 matrix-core rate (variant 3 runs
+# a third of its MFMAs on fp4 operands, whose own peak is four times
+# higher, so the fp16 figure is the stricter one).  "mfma" lists, per mask,
+# (instructions, flops each, published peak of their type in TFLOP/s).
+PEAK_FP4_MFMA_TFLOPS = 10100.0
 KERNELS = {1: {"kernel": "k_walsh<16,8,0>", "traffic": "k_walsh_16x16_traffic.json", "dtype": "i16",
-               "bound": "alu", "peak": PEAK_PK16_TOPS, "unit": "TOP/s", "mfma_per_mask": 0},
+               "bound": "alu", "peak": PEAK_PK16_TOPS, "unit": "TOP/s", "mfma": []},
            2: {"kernel": "k_walsh_mfma16<4>", "traffic": "k_walsh_mfma16_16x16_traffic.json", "dtype": "f16",
-               "bound": "mfma", "peak": PEAK_FP16_MFMA_TFLOPS, "unit": "TFLOP/s", "mfma_per_mask": 512}}
+               "bound": "mfma", "peak": PEAK_FP16_MFMA_TFLOPS, "unit": "TFLOP/s",
+               "mfma": [(512, MFMA_F16_FLOPS, PEAK_FP16_MFMA_TFLOPS)]},
+           3: {"kernel": "k_walsh_mx16", "traffic": "k_walsh_mx16_16x16_traffic.json", "dtype": "fp4+f16",
+               "bound": "mfma", "peak": PEAK_FP16_MFMA_TFLOPS, "unit": "TFLOP/s",
+               "mfma": [(256, 16 * 16 * 128 * 2, PEAK_FP4_MFMA_TFLOPS),
+                        (512, MFMA_F16_FLOPS, PEAK_FP16_MFMA_TFLOPS)]}}
 # The paper's own figures (Table 4, Fig. ch2; one Core i7 of 12 threads, 16 GB
 # DDR4, Windows 10, MSVC 2017, Table 3), quoted as context only.
 PAPER_CONTEXT = {
@@ -100,7 +109,8 @@ DEFAULT_VARIANT = 2
 # stay valid while the shared definitions before the first kernel and this
 # section are unchanged.
 KERNEL_SECTIONS = {1: ("// Main fused kernel", "void k_walsh(const KParams kp)"),
-                   2: ("// n = 16, max mode, matrix-core variant.", "void k_walsh_mfma16(const KParams kp)")}
+                   2: ("// n = 16, max mode, matrix-core variant.", "void k_walsh_mfma16(const KParams kp)"),
+                   3: ("// n = 16, max mode, three matrix-core passes", "void k_walsh_mx16(const KParams kp)")}
 
 
 def kernel_source_digest(variant):
@@ -305,9 +315,13 @@ def main():
             "achieved_is": "algorithmic add/sub of the transform (n per coefficient) per second",
             "int32_valu_peak": PEAK_INT32_TOPS, "int32_valu_frac": achieved_tops / PEAK_INT32_TOPS,
             "pk16_valu_peak": PEAK_PK16_TOPS, "pk16_valu_frac": achieved_tops / PEAK_PK16_TOPS}
-    if kinfo["mfma_per_mask"]:
-        issued = kinfo["mfma_per_mask"] * MFMA_F16_FLOPS * masks / (ev_mean * 1e-3) / 1e12
-        roof.update({"mfma_issued_tflops": issued, "mfma_issued_frac": issued / PEAK_FP16_MFMA_TFLOPS,
+    if kinfo["mfma"]:
+        # the matrix cores' own utilisation: issued flops of each type against its peak
+        sec = ev_mean * 1e-3
+        issued = sum(cnt * fl * masks for cnt, fl, _ in kinfo["mfma"]) / sec / 1e12
+        busy = sum(cnt * fl * masks / (pk * 1e12) for cnt, fl, pk in kinfo["mfma"]) / sec
+        roof.update({"mfma_issued_tflops": issued, "mfma_issued_frac": busy,
+                     "mfma_per_mask": [[cnt, fl] for cnt, fl, _ in kinfo["mfma"]],
                      "mfma_butterfly_peak": PEAK_MFMA_BUTTERFLY_TOPS,
                      "mfma_butterfly_frac": achieved_tops / PEAK_MFMA_BUTTERFLY_TOPS})
 
