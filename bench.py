@@ -62,6 +62,8 @@ def parse():
     ap.add_argument("--variant", type=int, default=0, choices=(0, 1, 2, 3),
                     help="butterfly engine for the 16x16 kernel: 0 library default, 1 VALU, 2 matrix cores "
                          "after popcount stages, 3 fp4 + fp16 matrix-core passes")
+    ap.add_argument("--rounds", type=int, default=0, choices=(0, 4, 8),
+                    help="with --variant 3: LDS exchange rounds per mask (0: library default)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters) and exit")
     ap.add_argument("--batched-only", action="store_true",
@@ -271,7 +273,7 @@ def main():
     stream = torch.cuda.current_stream(dev)
     sptr = int(stream.cuda_stream)
 
-    tuning = B.sbox_tuning(0, 0, 0, args.variant) if args.variant else None
+    tuning = B.sbox_tuning(args.rounds, 0, 0, args.variant) if args.variant else None
     variant = args.variant or DEFAULT_VARIANT
     kinfo = KERNELS[variant]
 

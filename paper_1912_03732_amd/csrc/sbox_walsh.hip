@@ -219,10 +219,16 @@ constexpr int kMfmaRounds = SBW_MFMA_ROUNDS;
 bool mfma_n(int n) { return n == 12 || n == 16; }
 int variant_of(const sbox_tuning* tun) { return (tun && tun->variant) ? tun->variant : kDefaultVariant; }
 bool use_mfma(int n, const sbox_tuning* tun) { return mfma_n(n) && variant_of(tun) >= 2; }
-// n = 16: variant 2 = fp16 passes after popcount stages, 3 = fp4 + fp16 passes
+// n = 16: variant 2 = fp16 passes after popcount stages, 3 = fp4 + fp16
+// passes, whose exchange rounds (4 or 8) tuning.split_p selects
+#ifndef SBW_MX_ROUNDS
+#define SBW_MX_ROUNDS 4
+#endif
 KFn mfma_kernel(int n, const sbox_tuning* tun) {
   if (n == 12) return &k_walsh_mfma12;
-  return variant_of(tun) == 3 ? &k_walsh_mx16 : &k_walsh_mfma16<kMfmaRounds>;
+  if (variant_of(tun) != 3) return &k_walsh_mfma16<kMfmaRounds>;
+  const int rounds = (tun && tun->split_p) ? tun->split_p : SBW_MX_ROUNDS;
+  return rounds == 8 ? &k_walsh_mx16<1> : &k_walsh_mx16<2>;
 }
 // masks a workgroup works on at once (thread groups per item slot)
 int mfma_groups(int n) { return n == 16 ? 1 : kWG / 64; }
@@ -614,9 +620,9 @@ sbox_status plan_batch(const sbox_job* jobs, int count, const sbox_tuning* tun, 
     ClassLaunch c{};
     c.n = n;
     c.layout = layout;
-    const int p = (tun && tun->split_p && n > 8) ? tun->split_p : default_split(n);
-    if (n > 8 && !split_valid(n, p)) return fail(SBOX_ERR_INVALID_ARG, "split_p=%d invalid for n=%d", p, n);
     const bool mc = layout == 0 && use_mfma(n, tun);
+    const int p = (tun && tun->split_p && n > 8 && !mc) ? tun->split_p : default_split(n);
+    if (n > 8 && !split_valid(n, p)) return fail(SBOX_ERR_INVALID_ARG, "split_p=%d invalid for n=%d", p, n);
     c.fn = mc ? mfma_kernel(n, tun) : lookup_kernel(n, p, mode_of(base_layout(layout)));
     if (!c.fn) return fail(SBOX_ERR_INVALID_ARG, "no kernel for n=%d split_p=%d layout=%d", n, p, layout);
     int occ = 1;
@@ -906,7 +912,10 @@ sbox_status sbox_walsh_nl_ex(const void* S, int n, int m, int s_elem_bytes, int3
       return fail(SBOX_ERR_INVALID_ARG, "the matrix-core variant covers n = 12 and 16 without a spectrum only");
     if (tuning->variant == 3 && !(n == 16 && layout == 0))
       return fail(SBOX_ERR_INVALID_ARG, "the fp4 matrix-core variant covers n = 16 without a spectrum only");
-    if (tuning->split_p && n > 8 && n <= 16 && !split_valid(n, tuning->split_p))
+    if (tuning->variant == 3 && tuning->split_p && tuning->split_p != 4 && tuning->split_p != 8)
+      return fail(SBOX_ERR_INVALID_ARG, "the fp4 matrix-core variant takes split_p = 4 or 8 exchange rounds");
+    if (tuning->split_p && n > 8 && n <= 16 && !(tuning->variant >= 2 && mfma_n(n) && layout == 0) &&
+        !split_valid(n, tuning->split_p))
       return fail(SBOX_ERR_INVALID_ARG, "split_p=%d invalid for n=%d", tuning->split_p, n);
     if (tuning->split_p && n <= 16 && n > 8 && layout != 0 && tuning->split_p != default_split(n))
       return fail(SBOX_ERR_INVALID_ARG, "spectrum output uses split_p=%d for n=%d", default_split(n), n);

@@ -862,13 +862,11 @@ __global__ __launch_bounds__(kWG, ROUNDS) void k_walsh_mfma16(const KParams kp) 
 //      through, the other four bits are transformed.  |value| <= 2^15.
 //   5. The maximum of |V| with abs modifiers.
 // Every bit of x is transformed once (7 + 5 + 4).  Rounds: the eight
-// column blocks of pass 1 two at a time, each pair carried through passes
-// 2 and 3, so one exchange holds a quarter of a mask (double-buffered).
+// column blocks of pass 1 one or two at a time (CPR), each carried through
+// passes 2 and 3, so one exchange holds an eighth or a quarter of a mask
+// (double-buffered).
 // ---------------------------------------------------------------------------
 typedef int i32x8 __attribute__((ext_vector_type(8)));
-
-constexpr int kMxSlotWords = 36;                       // 32 registers + 4 words of padding per lane
-constexpr int kMxBufWords = kWG * kMxSlotWords;        // one exchange buffer
 
 __device__ __forceinline__ uint32_t fp4_sign_word(int kbase, int a) {
   // e2m1 +1 (0x2) or -1 (0xA) for the 8 nibbles k = kbase + nib against output a
@@ -878,9 +876,22 @@ __device__ __forceinline__ uint32_t fp4_sign_word(int kbase, int a) {
   return w;
 }
 
-__global__ __launch_bounds__(kWG, 2) void k_walsh_mx16(const KParams kp) {
+// CPR: pass-1 column blocks per round (2: four rounds of 8 KiB per wave and
+// two workgroups per CU; 1: eight rounds of 4 KiB and fewer registers, so
+// more workgroups fit).
+template <int CPR>
+constexpr int mx_slot_words() { return 16 * CPR + 4; }  // a lane's registers + 16 bytes of padding
+template <int CPR>
+constexpr int mx_min_waves() { return CPR == 2 ? 2 : 3; }
+
+template <int CPR>
+__global__ __launch_bounds__(kWG, (mx_min_waves<CPR>())) void k_walsh_mx16(const KParams kp) {
   constexpr int NW = 8;
-  __shared__ __attribute__((aligned(16))) uint32_t lds[2 * kMxBufWords];
+  constexpr int ROUNDS = 8 / CPR;
+  constexpr int SLOT = mx_slot_words<CPR>();
+  constexpr int BUF = kWG * SLOT;  // one exchange buffer
+  static_assert(CPR == 1 || CPR == 2, "column blocks per round");
+  __shared__ __attribute__((aligned(16))) uint32_t lds[2 * BUF];
   __shared__ int red[64 * 4];  // per mask of a run of 64: the 4 wave maxima
   __shared__ long long s_item;
 
@@ -890,13 +901,18 @@ __global__ __launch_bounds__(kWG, 2) void k_walsh_mx16(const KParams kp) {
   const int C = kp.chunk;
   const int col = lane & 15, g = lane >> 4;
 
-  // Pass-1 B operands: block cb, register p, nibble: K slot
-  // k = nib + 8 p + 32 g against output 16 cb + col.
-  uint32_t B1[8][4];
+  // Pass-1 B operand of block cb, register p: nibble nib is slot
+  // k = nib + 8 p + 32 g against output 16 cb + col.  The sign splits into a
+  // part of (nib, p, col, cb & 1) and parity(g & (cb >> 1)), which flips
+  // every nibble's sign bit.
+  uint32_t B1b[2][4];
 #pragma unroll
-  for (int cb = 0; cb < 8; ++cb)
+  for (int c0 = 0; c0 < 2; ++c0)
 #pragma unroll
-    for (int p = 0; p < 4; ++p) B1[cb][p] = fp4_sign_word(8 * p + 32 * g, 16 * cb + col);
+    for (int p = 0; p < 4; ++p) B1b[c0][p] = fp4_sign_word(8 * p, 16 * c0 + col);
+  uint32_t gflip[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) gflip[c] = (__builtin_popcount(g & c) & 1) ? 0x88888888u : 0u;
   // Pass-2 B operands: the two 16-column halves of H_32, slot kappa = j + 8 g.
   f16x8 hb0, hb1;
   // Pass-3 B operands: slot j = h + 2 p3 (h passed through) + 8 g; MFMA hf keeps h = hf.
@@ -915,8 +931,8 @@ __global__ __launch_bounds__(kWG, 2) void k_walsh_mx16(const KParams kp) {
   const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
   // exchange slots: written as (lane >> 4, wave, lane & 15), read with the
   // wave and the lane's upper bits swapped
-  const int wslot = ((g * 4 + wave) * 16 + col) * kMxSlotWords;
-  const int rslot = ((wave * 4 + g) * 16 + col) * kMxSlotWords;
+  const int wslot = ((g * 4 + wave) * 16 + col) * SLOT;
+  const int rslot = ((wave * 4 + g) * 16 + col) * SLOT;
 
   for (;;) {
     if (tid == 0) s_item = (long long)atomicAdd(kp.queue, 1);
@@ -957,10 +973,14 @@ __global__ __launch_bounds__(kWG, 2) void k_walsh_mx16(const KParams kp) {
             if ((gk >> i) & 1) load_words<NW>(G, jd.F + (long long)i * jd.nwords + wb, true);
         }
       } else if (inrange) {
+        if constexpr (CPR == 2) {
 #pragma unroll
-        for (int w = 0; w < NW; ++w) G[w] ^= Fn[w];
+          for (int w = 0; w < NW; ++w) G[w] ^= Fn[w];
+        } else {  // no prefetch register set: the slice is read when it is needed
+          load_words<NW>(G, jd.F + (long long)__builtin_ctzll((unsigned long long)k) * jd.nwords + wb, true);
+        }
       }
-      if (step + 1 < C && k + 1 < kend) {
+      if (CPR == 2 && step + 1 < C && k + 1 < kend) {
         const int i = __builtin_ctzll((unsigned long long)(k + 1));
         load_words<NW>(Fn, jd.F + (long long)i * jd.nwords + wb, false);
       }
@@ -981,15 +1001,18 @@ __global__ __launch_bounds__(kWG, 2) void k_walsh_mx16(const KParams kp) {
           A[3][x7][p + 4] = 0;
         }
       float m0 = 0.0f, m1 = 0.0f;
+      // eight rounds stay a loop: unrolled, the rounds' live ranges overlap
+#pragma unroll (CPR == 2 ? ROUNDS : 1)
+      for (int r = 0; r < ROUNDS; ++r) {
+        uint32_t* buf = lds + (r & 1) * BUF;
+        // ---- pass 1 for the round's column blocks, cast, pass 2
+        uint32_t X[CPR][2][2][4];  // [block][hf2][s][x8 x9]: pass-2 results as fp16 pairs (pass-3 operands)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        uint32_t* buf = lds + (r & 1) * kMxBufWords;
-        // ---- pass 1 for column blocks 2r, 2r + 1, cast, pass 2
-        uint32_t X[2][2][2][4];  // [block][hf2][s][x8 x9]: pass-2 results as fp16 pairs (pass-3 operands)
-#pragma unroll
-        for (int cl = 0; cl < 2; ++cl) {
-          const int cb = 2 * r + cl;
-          const i32x8 b = {(int)B1[cb][0], (int)B1[cb][1], (int)B1[cb][2], (int)B1[cb][3], 0, 0, 0, 0};
+        for (int cl = 0; cl < CPR; ++cl) {
+          const int cb = CPR * r + cl;
+          const uint32_t fl = gflip[cb >> 1];
+          const i32x8 b = {(int)(B1b[cb & 1][0] ^ fl), (int)(B1b[cb & 1][1] ^ fl), (int)(B1b[cb & 1][2] ^ fl),
+                           (int)(B1b[cb & 1][3] ^ fl), 0, 0, 0, 0};
           f32x4 D[4][2];
 #pragma unroll
           for (int t = 0; t < 4; ++t)
@@ -1011,21 +1034,21 @@ __global__ __launch_bounds__(kWG, 2) void k_walsh_mx16(const KParams kp) {
         }
         // ---- exchange (double-buffered: one barrier per round)
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
+        for (int q = 0; q < 4 * CPR; ++q) {
           const int cl = q >> 2, hf = (q >> 1) & 1, s = q & 1;
           *reinterpret_cast<uint4*>(buf + wslot + 4 * q) =
               uint4{X[cl][hf][s][0], X[cl][hf][s][1], X[cl][hf][s][2], X[cl][hf][s][3]};
         }
         __syncthreads();
-        uint32_t Y[8][4];
+        uint32_t Y[4 * CPR][4];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
+        for (int q = 0; q < 4 * CPR; ++q) {
           const uint4 v = *reinterpret_cast<const uint4*>(buf + rslot + 4 * q);
           Y[q][0] = v.x; Y[q][1] = v.y; Y[q][2] = v.z; Y[q][3] = v.w;
         }
         // ---- pass 3 and the maximum
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
+        for (int q = 0; q < 4 * CPR; ++q) {
           const f16x8 av = as_f16x8(Y[q][0], Y[q][1], Y[q][2], Y[q][3]);
           const f32x4 d0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(av, hc0, zero, 0, 0, 0);
           const f32x4 d1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(av, hc1, zero, 0, 0, 0);

@@ -95,9 +95,9 @@ def test_criteria_inversion_and_nl_agree_with_fused_path():
 
 @pytest.mark.parametrize("n,m", [(15, 3), (15, 4), (16, 2), (16, 3)])
 def test_criteria_large_random(n, m):
-    """n = 15 runs the register-blocked kernel with one 512-lane group per
-    workgroup; n = 16 the slab path (spectrum rows, squares, second
-    transform, row reductions): bit-exact against the oracle."""
+    """n = 15 and 16 run the register-blocked kernel with one 512- or
+    1,024-lane workgroup per mask (both transforms on one compute unit):
+    bit-exact against the oracle."""
     _check(table(n, m, 12500 + n * m), n, m)
 
 

@@ -470,9 +470,10 @@ def test_single_call_graph_replay(n, m, spectrum):
     assert int(nl.item()) == oracle.walsh_nl(new, n, m)[0]
 
 
+@pytest.mark.parametrize("rounds", [4, 8])
 @pytest.mark.parametrize("m,kind", [(1, "random"), (4, "random"), (9, "random"), (16, "perm"), (16, "inv"),
                                     (16, "const"), (16, "affine"), (16, "zero"), (19, "random")])
-def test_fp4_matrix_core_variant_16(m, kind):
+def test_fp4_matrix_core_variant_16(m, kind, rounds):
     """n = 16 fused maximum on three matrix-core passes (fp4 then fp16,
     tuning variant 3), bit-exact; the constant, affine and all-zero boxes
     reach |W| = 2^16 at a = 0 and elsewhere."""
@@ -489,7 +490,7 @@ def test_fp4_matrix_core_variant_16(m, kind):
         S = np.zeros(1 << 16, np.uint16)
     else:
         S = table(16, m, 15500 + m)
-    nl, mx = check_against_oracle(S, 16, m, nthreads=NT, tuning=B.sbox_tuning(0, 0, 0, 3))
+    nl, mx = check_against_oracle(S, 16, m, nthreads=NT, tuning=B.sbox_tuning(rounds, 0, 0, 3))
     if kind == "inv":
         assert nl == 32512
     if kind == "const":
@@ -498,10 +499,11 @@ def test_fp4_matrix_core_variant_16(m, kind):
         assert nl == 0
 
 
+@pytest.mark.parametrize("rounds", [4, 8])
 @pytest.mark.parametrize("chunk,grid", [(1, 1), (7, 33), (64, 0), (200, 5)])
-def test_fp4_matrix_core_launch_shapes(chunk, grid):
+def test_fp4_matrix_core_launch_shapes(chunk, grid, rounds):
     S = table(16, 10, 15600 + chunk)
-    check_against_oracle(S, 16, 10, nthreads=NT, tuning=B.sbox_tuning(0, chunk, grid, 3))
+    check_against_oracle(S, 16, 10, nthreads=NT, tuning=B.sbox_tuning(rounds, chunk, grid, 3))
 
 
 def test_fp4_matrix_core_in_a_plan():

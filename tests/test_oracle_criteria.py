@@ -23,20 +23,42 @@ def test_wiener_khinchin(n, m):
         assert r[0] == 1 << n
 
 
-def test_criteria_match_spectrum_and_definitions():
-    n, m = 7, 5
-    S = inputs.random_function(n, m, inputs.rng(901))
+def _bent_and_quadratic(n):
+    """n even, m = 3: component 1 the bent x_lo . x_hi (r(d) = 0 for d != 0),
+    component 2 the quadratic x0 x1 (every d with d0 = d1 = 0 is a linear
+    structure), component 3 the balanced x0 ^ x2 x3: per-mask propagation
+    weights 1, n + 1 and mixtures of them."""
+    h = n // 2
+    x = np.arange(1 << n)
+    f1 = popcount((x & ((1 << h) - 1)) & (x >> h)) & 1
+    f2 = (x & 1) & ((x >> 1) & 1)
+    f3 = (x & 1) ^ (((x >> 2) & 1) & ((x >> 3) & 1))
+    return f1 | (f2 << 1) | (f3 << 2)
+
+
+@pytest.mark.parametrize("n,m,kind", [(7, 5, "random"), (6, 3, "structured"), (8, 3, "structured")])
+def test_criteria_match_spectrum_and_definitions(n, m, kind):
+    """Every per-mask output against the stored spectrum (w0, minwt) and the
+    autocorrelation summed from its definition (acmax, pcwt)."""
+    S = inputs.random_function(n, m, inputs.rng(901)) if kind == "random" else _bent_and_quadratic(n)
     summ, per = oracle.criteria(S, n, m)
     Wt = oracle.spectrum(S, n, m, oracle.B_MAJOR)
     wts = popcount(np.arange(1 << n))
+    pcw = set()
     for b in range(1, 1 << m):
         assert per["w0"][b] == Wt[b, 0]
         nz = [int(wts[a]) for a in range(1, 1 << n) if Wt[b, a] != 0]
         assert per["minwt"][b] == (min(nz) if nz else n + 1)
         r = oracle.autocorrelation(S, n, m, b)
         assert per["acmax"][b] == int(np.abs(r[1:]).max())
+        nzd = [int(wts[d]) for d in range(1, 1 << n) if r[d] != 0]
+        assert per["pcwt"][b] == (min(nzd) if nzd else n + 1)
+        pcw.add(int(per["pcwt"][b]))
     assert summ["nl"] == oracle.walsh_nl(S, n, m)[0]
     assert summ["unbalanced"] == int(np.count_nonzero(Wt[1:, 0]))
+    assert summ["pc_order"] == min(pcw) - 1
+    if kind == "structured":
+        assert per["pcwt"][1] == n + 1 and per["pcwt"][2] == 1 and len(pcw) >= 2
 
 
 @pytest.mark.parametrize("n", [4, 6, 8])
