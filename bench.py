@@ -106,7 +106,7 @@ PAPER_CONTEXT = {
     "fwht_16x16_ms": {"primary": 2496726, "a_transposed": 326331, "b_10_threads": 62756, "c_fused_nl": 83013},
     "nl_16x16_ms": {"primary": 46741627, "a_transposed": 539120, "b_10_threads": 539120, "c_fused_nl": 83015},
 }
-DEFAULT_VARIANT = 2
+DEFAULT_VARIANT = 3
 # Where each kernel's source starts and which function ends it: the counters
 # stay valid while the shared definitions before the first kernel and this
 # section are unchanged.

@@ -78,14 +78,15 @@ typedef enum {
  *             walks per work item.
  *   grid    : number of persistent workgroups (0: fill every CU).
  *   variant : butterfly engine for the n = 12 and n = 16 fused maximum (no
- *             spectrum): 0 the library's choice (currently 2), 1 packed
+ *             spectrum): 0 the library's choice (currently 3), 1 packed
  *             16-bit VALU butterflies, 2 matrix cores (fp16 MFMA Hadamard
  *             blocks after popcount stages, exact; split_p does not apply),
- *             3 (n = 16 only) three matrix-core passes, the first on fp4
- *             operands taken straight from the table's bits, then two on
- *             fp16 (exact); other sizes and modes accept 0 or 1 only.
- *             Batched launches and plans apply it to their n = 12 and
- *             n = 16 boxes (variant 3 runs n = 12 boxes as variant 2).
+ *             3 matrix cores without popcount stages: a first pass on fp4
+ *             operands taken straight from the table's bits, then fp16
+ *             passes (two at n = 16, where split_p = 4 or 8 picks the LDS
+ *             exchange rounds; one at n = 12, one wave per mask); exact.
+ *             Other sizes and modes accept 0 or 1 only.  Batched launches
+ *             and plans apply it to their n = 12 and n = 16 boxes.
  */
 typedef struct sbox_tuning {
     int32_t split_p;

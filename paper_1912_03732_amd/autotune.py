@@ -45,10 +45,13 @@ def candidates(n: int, m: int, cus: int = 256) -> List[Tuple[int, int, int]]:
         for c in chunks:
             for g in grids:
                 out.append((p if n > 8 else 0, c, g, 1 if n in (12, 16) else 0))
-    if n in (12, 16):  # the matrix-core engine
+    if n in (12, 16):  # the matrix-core engines (at n = 16 also fp4 + fp16 with 4 or 8 exchange rounds)
         for c in chunks:
             for g in grids:
                 out.append((0, c, g, 2))
+                if n == 16:
+                    for r in (4, 8):
+                        out.append((r, c, g, 3))
     return out
 
 

@@ -169,7 +169,8 @@ sbox_status check_layout(int layout, int n, int m, const int32_t* spec) {
 int elem_bytes_for(int m) { return m <= 8 ? 1 : (m <= 16 ? 2 : 4); }
 
 size_t f_bytes(int n, int m) {
-  const size_t nwords = n >= 5 ? ((size_t)1 << (n - 5)) : 1;
+  // n = 12: room for the sparse words of the fp4 engine (16 inputs a word)
+  const size_t nwords = n == 12 ? 256 : (n >= 5 ? ((size_t)1 << (n - 5)) : 1);
   return align256((size_t)m * nwords * 4);
 }
 
@@ -208,9 +209,11 @@ long long inverse_gray(long long j) {
 }
 
 // Butterfly engine of the n = 12 and n = 16 fused maximum: the library
-// default is the matrix-core kernel (variant 2); variant 1 selects the packed
-// 16-bit VALU one.
-constexpr int kDefaultVariant = 2;
+// default is variant 3, which at n = 16 runs the fp4 + fp16 matrix-core
+// kernel and at n = 12 the matrix-core kernel of variant 2; variant 2 at
+// n = 16 is the matrix-core kernel after popcount stages, variant 1 the
+// packed 16-bit VALU one.
+constexpr int kDefaultVariant = 3;
 // LDS exchange rounds of the n = 16 matrix-core kernel (2: 64 KiB, 4: 32 KiB per workgroup)
 #ifndef SBW_MFMA_ROUNDS
 #define SBW_MFMA_ROUNDS 4
@@ -224,8 +227,10 @@ bool use_mfma(int n, const sbox_tuning* tun) { return mfma_n(n) && variant_of(tu
 #ifndef SBW_MX_ROUNDS
 #define SBW_MX_ROUNDS 4
 #endif
+// The n = 12 fp4 engine reads sparse words (kWordsFp4).
+bool fp4_words(int n, const sbox_tuning* tun) { return n == 12 && use_mfma(n, tun) && variant_of(tun) == 3; }
 KFn mfma_kernel(int n, const sbox_tuning* tun) {
-  if (n == 12) return &k_walsh_mfma12;
+  if (n == 12) return variant_of(tun) == 3 ? &k_walsh_mx12 : &k_walsh_mfma12;
   if (variant_of(tun) != 3) return &k_walsh_mfma16<kMfmaRounds>;
   const int rounds = (tun && tun->split_p) ? tun->split_p : SBW_MX_ROUNDS;
   return rounds == 8 ? &k_walsh_mx16<1> : &k_walsh_mx16<2>;
@@ -322,7 +327,8 @@ sbox_status run_single(const void* S, int n, int m, int eb, int32_t* maxabs, int
   if (s) return s;
   int* queue = reinterpret_cast<int*>(ws);
   uint32_t* F = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(ws) + kQueueBytes);
-  const int nwords = n >= 5 ? 1 << (n - 5) : 1;
+  const bool sparse = layout == 0 && !hist && fp4_words(n, tun);
+  const int nwords = sparse ? 256 : (n >= 5 ? 1 << (n - 5) : 1);
 
   if (use_big(n, layout)) {
     // init (NL, maxabs[0], queue), then the x_hi-inner bit-slicing and the kernel
@@ -351,6 +357,7 @@ sbox_status run_single(const void* S, int n, int m, int eb, int32_t* maxabs, int
   jd.nwords = nwords;
   jd.s_elem_bytes = eb;
   jd.wscale = wscale;
+  jd.flags = sparse ? kWordsFp4 : 0;
   // one launch: start values (queue counters, NL, maxabs[0], b = 0 spectrum
   // row) in workgroup 0, bit-sliced component words in the others
   {
@@ -658,7 +665,9 @@ sbox_status plan_batch(const sbox_job* jobs, int count, const sbox_tuning* tun, 
       d.item_begin = items;
       d.n = j.n;
       d.m = j.m;
-      d.nwords = j.n >= 5 ? 1 << (j.n - 5) : 1;
+      const bool sparse = mc && fp4_words(j.n, tun);
+      d.nwords = sparse ? 256 : (j.n >= 5 ? 1 << (j.n - 5) : 1);
+      d.flags = sparse ? kWordsFp4 : 0;
       d.s_elem_bytes = j.s_elem_bytes;
       d.wscale = wscale_of(j.layout);
       const long long per_item = (long long)groups * c.chunk;
@@ -880,7 +889,7 @@ extern "C" {
 
 const char* sbox_last_error(void) { return g_last_error.c_str(); }
 
-const char* sbox_version(void) { return "1.0.0"; }
+const char* sbox_version(void) { return "1.1.0"; }
 
 size_t sbox_walsh_nl_workspace_bytes(int n, int m, int layout) {
   if (n < 1 || n > 24 || m < 1 || m > 24 || n + m > 40) return 0;
@@ -910,9 +919,9 @@ sbox_status sbox_walsh_nl_ex(const void* S, int n, int m, int s_elem_bytes, int3
       return fail(SBOX_ERR_INVALID_ARG, "tuning variant %d (0, 1, 2 or 3)", tuning->variant);
     if (tuning->variant == 2 && !(mfma_n(n) && layout == 0))
       return fail(SBOX_ERR_INVALID_ARG, "the matrix-core variant covers n = 12 and 16 without a spectrum only");
-    if (tuning->variant == 3 && !(n == 16 && layout == 0))
-      return fail(SBOX_ERR_INVALID_ARG, "the fp4 matrix-core variant covers n = 16 without a spectrum only");
-    if (tuning->variant == 3 && tuning->split_p && tuning->split_p != 4 && tuning->split_p != 8)
+    if (tuning->variant == 3 && !(mfma_n(n) && layout == 0))
+      return fail(SBOX_ERR_INVALID_ARG, "the fp4 matrix-core variant covers n = 12 and 16 without a spectrum only");
+    if (tuning->variant == 3 && n == 16 && tuning->split_p && tuning->split_p != 4 && tuning->split_p != 8)
       return fail(SBOX_ERR_INVALID_ARG, "the fp4 matrix-core variant takes split_p = 4 or 8 exchange rounds");
     if (tuning->split_p && n > 8 && n <= 16 && !(tuning->variant >= 2 && mfma_n(n) && layout == 0) &&
         !split_valid(n, tuning->split_p))

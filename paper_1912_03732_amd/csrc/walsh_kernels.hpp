@@ -71,8 +71,11 @@ struct JobDesc {
   int nwords;            // words per slice (2^(n-5), at least 1)
   int s_elem_bytes;
   int wscale;            // stored value = wscale * (-W/2): -2 for W, -1 for the LAT (W/2)
-  int pad_;
+  int flags;             // kWordsFp4: F holds the sparse words of the n = 12 fp4 engine
 };
+
+// JobDesc::flags
+constexpr int kWordsFp4 = 1;
 
 struct KParams {
   const JobDesc* jobs;   // device job table, or null to use job0
@@ -1235,6 +1238,134 @@ __global__ __launch_bounds__(kWG, 4) void k_walsh_mfma12(const KParams kp) {
 }
 
 // ---------------------------------------------------------------------------
+// n = 12, max mode, two matrix-core passes (fp4, then fp16): one wave per
+// mask, four masks per workgroup, no LDS and no barrier inside a mask.
+//
+// The table is bit-sliced into sparse words (bitslice_words_fp4): word w
+// holds x = 16 w + j at bit 4 (j >> 1) + 1 + (j & 1), so x0 picks bit 1 or
+// 2 of a nibble and x1..x3 the nibble; lane l holds words 4 l .. 4 l + 3
+// (x4, x5 the register, x6..x11 the lane).  As in k_walsh_mx16 the bits
+// themselves are transformed and V = T - 2^11 [a = 0] = -W / 2 is tracked.
+//   1. Pass 1, v_mfma_scale_f32_16x16x128_f8f6f4 on e2m1: for x0 = 0, 1 the
+//      operand is the four words ANDed with 0x22222222 or 0x44444444 (e2m1
+//      1.0 or 2.0, operand scale 2^0 or 2^-1).  K slots (x1, x2, x3 | x4, x5 |
+//      x10, x11), rows x6..x9, eight 16-column blocks of H_128; -64 at
+//      column 0 of block 0 removes 2^11 over the 2^5 tiles reaching output 0.
+//      |value| <= 64.
+//   2. Pass 2, v_mfma_f32_16x16x32_f16: per column block the two results over
+//      x0 become the operand's halves, the tile rows x6, x7 its registers and
+//      the lane's tile rows x8, x9 its K slots.  |value| <= 2048.
+//   3. The maximum of |V| with abs modifiers.
+// Every bit of x is transformed once (7 + 5).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kWG, 5) void k_walsh_mx12(const KParams kp) {
+  constexpr int NW = 4;
+  constexpr int GPW = kWG / 64;  // masks (waves) per workgroup
+  __shared__ long long s_item;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int C = kp.chunk;
+  const int col = lane & 15, g = lane >> 4;
+
+  uint32_t B1b[2][4];
+#pragma unroll
+  for (int c0 = 0; c0 < 2; ++c0)
+#pragma unroll
+    for (int p = 0; p < 4; ++p) B1b[c0][p] = fp4_sign_word(8 * p, 16 * c0 + col);
+  uint32_t gflip[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) gflip[c] = (__builtin_popcount(g & c) & 1) ? 0x88888888u : 0u;
+  f16x8 hb0, hb1;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int kappa = j + 8 * g;
+    hb0[j] = hsign(kappa & col);
+    hb1[j] = hsign(kappa & (col + 16));
+  }
+  const float fix = col == 0 ? -64.0f : 0.0f;
+  const f32x4 cfix = {fix, fix, fix, fix};
+  const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+
+  for (;;) {
+    if (tid == 0) s_item = (long long)atomicAdd(kp.queue, 1);
+    __syncthreads();
+    const long long item = __builtin_amdgcn_readfirstlane((int)s_item);
+    __syncthreads();
+    if (item >= kp.total_items) break;
+    JobDesc jd;
+    long long li;
+    if (kp.jobs == nullptr) {
+      jd = kp.job0;
+      li = item;
+    } else {
+      int lo = 0, hi = kp.njobs - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (kp.jobs[mid].item_begin <= item) lo = mid; else hi = mid - 1;
+      }
+      jd = kp.jobs[lo];
+      li = item - jd.item_begin;
+    }
+    const long long kfirst = (li * GPW + wave) * (long long)C;
+    const long long kend = 1LL << jd.m;
+    const long long wb = (long long)lane * NW;
+    const int n = jd.n;
+    int runmin = 0x7fffffff;
+    uint32_t G[NW], Fn[NW];
+
+    for (int step = 0; step < C; ++step) {
+      const long long k = kfirst + step;
+      if (k >= kend) break;  // wave-uniform
+      if (step == 0) {
+#pragma unroll
+        for (int w = 0; w < NW; ++w) G[w] = 0;
+        const long long gk = gray(k);
+        for (int i = 0; i < jd.m; ++i)
+          if ((gk >> i) & 1) load_words<NW>(G, jd.F + (long long)i * jd.nwords + wb, true);
+      } else {
+#pragma unroll
+        for (int w = 0; w < NW; ++w) G[w] ^= Fn[w];
+      }
+      if (step + 1 < C && k + 1 < kend) {
+        const int i = __builtin_ctzll((unsigned long long)(k + 1));
+        load_words<NW>(Fn, jd.F + (long long)i * jd.nwords + wb, false);
+      }
+      const i32x8 a0 = {(int)(G[0] & 0x22222222u), (int)(G[1] & 0x22222222u), (int)(G[2] & 0x22222222u),
+                        (int)(G[3] & 0x22222222u), 0, 0, 0, 0};
+      const i32x8 a1 = {(int)(G[0] & 0x44444444u), (int)(G[1] & 0x44444444u), (int)(G[2] & 0x44444444u),
+                        (int)(G[3] & 0x44444444u), 0, 0, 0, 0};
+      float m0 = 0.0f, m1 = 0.0f;
+#pragma unroll
+      for (int cb = 0; cb < 8; ++cb) {
+        const uint32_t fl = gflip[cb >> 1];
+        const i32x8 b = {(int)(B1b[cb & 1][0] ^ fl), (int)(B1b[cb & 1][1] ^ fl), (int)(B1b[cb & 1][2] ^ fl),
+                         (int)(B1b[cb & 1][3] ^ fl), 0, 0, 0, 0};
+        const f32x4 d0 = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a0, b, cb == 0 ? cfix : zero, 4, 4, 0,
+                                                                          127, 0, 127);
+        const f32x4 d1 = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a1, b, cb == 0 ? cfix : zero, 4, 4, 0,
+                                                                          126, 0, 127);
+        const f16x8 av = as_f16x8(pk_cvt_f16(d0[0], d1[0]), pk_cvt_f16(d0[1], d1[1]), pk_cvt_f16(d0[2], d1[2]),
+                                  pk_cvt_f16(d0[3], d1[3]));
+        const f32x4 e0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(av, hb0, zero, 0, 0, 0);
+        const f32x4 e1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(av, hb1, zero, 0, 0, 0);
+        m0 = fmaxf(fmaxf(m0, fabsf(e0[0])), fabsf(e1[0]));
+        m1 = fmaxf(fmaxf(m1, fabsf(e0[1])), fabsf(e1[1]));
+        m0 = fmaxf(fmaxf(m0, fabsf(e0[2])), fabsf(e1[2]));
+        m1 = fmaxf(fmaxf(m1, fabsf(e0[3])), fabsf(e1[3]));
+      }
+      const int mx = wave_max((int)fmaxf(m0, m1));
+      if (lane == 0 && k != 0) {
+        if (jd.maxabs) jd.maxabs[(uint32_t)gray(k)] = 2 * mx;
+        runmin = min(runmin, (1 << (n - 1)) - mx);
+      }
+    }
+    if (lane == 0 && runmin != 0x7fffffff) atomicMin(jd.nl, runmin);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // n = 16 + L, 1 <= L <= 4, max mode: recompute instead of materialising.
 //
 // Write x = (x_hi : L bits, x_lo : 16 bits).  For a fixed high output index
@@ -1447,6 +1578,30 @@ __device__ void bitslice_words(const void* S, int n, int m, uint32_t* F, int nwo
   }
 }
 
+// Sparse words of the n = 12 fp4 engine: word w holds x = 16 w + j at bit
+// 4 (j >> 1) + 1 + (j & 1) (bits 1 and 2 of each nibble, whose e2m1 values
+// are 1.0 and 2.0), 16 inputs a word.
+template <int EB>
+__device__ void bitslice_words_fp4(const void* S, int m, uint32_t* F, int nwords, int w) {
+  uint32_t v[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) v[j] = load_entry<EB>(S, (long long)w * 16 + j);
+  for (int i = 0; i < m; ++i) {
+    uint32_t word = 0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) word |= ((v[j] >> i) & 1u) << (4 * (j >> 1) + 1 + (j & 1));
+    F[(long long)i * nwords + w] = word;
+  }
+}
+
+// The words of one job in its layout.
+template <int EB>
+__device__ __forceinline__ void bitslice_job(const JobDesc& jd, int w) {
+  uint32_t* F = const_cast<uint32_t*>(jd.F);
+  if (jd.flags & kWordsFp4) bitslice_words_fp4<EB>(jd.S, jd.m, F, jd.nwords, w);
+  else bitslice_words<EB>(jd.S, jd.n, jd.m, F, jd.nwords, w);
+}
+
 // Bit-slicing for k_walsh_big: word w = x_lo >> B holds, at bit
 // j = x_lo_low + 2^B * x_hi, bit i of S[x_hi * 2^16 + x_lo].
 template <int EB>
@@ -1473,10 +1628,9 @@ __global__ __launch_bounds__(256) void k_bitslice_big(const void* S, int L, int 
 __global__ __launch_bounds__(64) void k_bitslice_jobs(const JobDesc* jobs) {
   const JobDesc jd = jobs[blockIdx.y];
   for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < jd.nwords; w += gridDim.x * blockDim.x) {
-    uint32_t* F = const_cast<uint32_t*>(jd.F);
-    if (jd.s_elem_bytes == 1) bitslice_words<1>(jd.S, jd.n, jd.m, F, jd.nwords, w);
-    else if (jd.s_elem_bytes == 2) bitslice_words<2>(jd.S, jd.n, jd.m, F, jd.nwords, w);
-    else bitslice_words<4>(jd.S, jd.n, jd.m, F, jd.nwords, w);
+    if (jd.s_elem_bytes == 1) bitslice_job<1>(jd, w);
+    else if (jd.s_elem_bytes == 2) bitslice_job<2>(jd, w);
+    else bitslice_job<4>(jd, w);
   }
 }
 
@@ -2214,7 +2368,7 @@ __global__ __launch_bounds__(256) void k_prep_single(JobDesc jd, int* queue, int
     return;
   }
   const int w = (blockIdx.x - 1) * blockDim.x + threadIdx.x;
-  if (w < jd.nwords) bitslice_words<EB>(jd.S, jd.n, jd.m, const_cast<uint32_t*>(jd.F), jd.nwords, w);
+  if (w < jd.nwords) bitslice_job<EB>(jd, w);
 }
 
 // Zero `count` ints (queue counters, per-batch maxima) without a memset node.

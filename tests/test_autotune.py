@@ -26,7 +26,9 @@ def test_candidates_cover_chunks_and_grids():
     assert (6, 1, 0, 0) in c10 and {v for _, _, _, v in c10} == {0}
     c16 = autotune.candidates(16, 16)
     assert {p for p, _, _, v in c16 if v == 1} == {8} and {g for _, _, g, _ in c16} == {0}
-    assert {v for _, _, _, v in c16} == {1, 2}
+    assert {v for _, _, _, v in c16} == {1, 2, 3}
+    assert {p for p, _, _, v in c16 if v == 3} == {4, 8}  # the fp4 engine's exchange rounds
+    assert 3 not in {v for _, _, _, v in c}
     assert {p for p, _, _, _ in autotune.candidates(7, 7)} == {0}
 
 

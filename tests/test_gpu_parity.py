@@ -521,3 +521,73 @@ def test_fp4_matrix_core_in_a_plan():
         onl, omx = oracle.walsh_nl(S, n, m, nthreads=NT)
         assert nl[i] == onl and np.array_equal(plan.maxabs[i].cpu().numpy(), omx), (i, n, m)
     plan.close()
+
+
+def test_a_major_slabs_graph_replay():
+    """n = 13, m = 16: four blocks of 2^14 masks through the int16 slab, the
+    call captured into a HIP graph and replayed three times (with eager
+    work between): every replay equals the oracle's columns."""
+    import torch
+    n, m = 13, 16
+    S = table(n, m, 13070)
+    t = dev_table(S, m)
+    ws = B.Workspace(B.sbox_walsh_nl_workspace_bytes(n, m, B.SPECTRUM_A_MAJOR))
+    spec = torch.empty(1 << (n + m), dtype=torch.int32, device="cuda")
+    nl = torch.empty(1, dtype=torch.int32, device="cuda")
+    g = inputs.rng(13071)
+    cols = [0, 1, 1 << 14, (1 << 15) + 7, (1 << 16) - 1] + [int(v) for v in g.integers(1, 1 << 16, size=6)]
+    refs = {b: oracle.walsh_column(S, n, m, b) for b in cols}
+
+    def check(tag):
+        W = spec.view(1 << n, 1 << m)
+        for b in cols:
+            assert np.array_equal(W[:, b].cpu().numpy(), refs[b]), (tag, b)
+
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=s):
+        st = B.sbox_walsh_nl_ex(t.data_ptr(), n, m, t.element_size(), 0, nl.data_ptr(), spec.data_ptr(),
+                                B.SPECTRUM_A_MAJOR, ws.ptr, ws.nbytes, None, int(s.cuda_stream))
+    assert st == B.SBOX_OK, B.last_error()
+    for rep in range(3):
+        spec.zero_()
+        nl.fill_(-1)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        check("replay %d" % rep)
+    assert int(nl.item()) == oracle.walsh_nl(S, n, m, nthreads=NT)[0]
+    del spec
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("m,kind", [(1, "random"), (5, "random"), (12, "perm"), (12, "inv"), (12, "const"),
+                                    (12, "affine"), (12, "zero"), (17, "random"), (20, "random")])
+def test_fp4_matrix_core_variant_12(m, kind):
+    """n = 12 on two matrix-core passes (fp4 on sparse words, then fp16; one
+    wave per mask), bit-exact; structured boxes reach |W| = 2^12."""
+    if kind == "perm":
+        S = inputs.permutation(12, inputs.rng(6101))
+    elif kind == "inv":
+        S = inputs.gf_inversion(12)
+    elif kind == "const":
+        S = (inputs.permutation(12, inputs.rng(6102)) & 0x7FF).astype(np.uint16)
+    elif kind == "affine":
+        x = np.arange(1 << 12)
+        S = (x ^ (x << 2) ^ (x >> 5) ^ 0x5A5) & 0xFFF
+    elif kind == "zero":
+        S = np.zeros(1 << 12, np.uint16)
+    else:
+        S = table(12, m, 16500 + m)
+    nl, mx = check_against_oracle(S, 12, m, nthreads=NT, tuning=B.sbox_tuning(0, 0, 0, 3))
+    if kind == "inv":
+        assert nl == (1 << 11) - (1 << 6)
+    if kind in ("const", "affine", "zero"):
+        assert nl == 0
+
+
+@pytest.mark.parametrize("chunk,grid", [(1, 1), (3, 7), (64, 0), (9, 1000)])
+def test_fp4_matrix_core_12_launch_shapes(chunk, grid):
+    S = table(12, 11, 16600 + chunk)
+    check_against_oracle(S, 12, 11, nthreads=NT, tuning=B.sbox_tuning(0, chunk, grid, 3))
