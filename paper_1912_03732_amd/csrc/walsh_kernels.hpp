@@ -1851,7 +1851,7 @@ __device__ __forceinline__ int crit_group_reduce(int v, int* xr, int l) {
   } else {
     constexpr int NW = GL / 64;  // waves of the group, <= 16
     v = group_reduce<64, IS_MAX>(v);
-    if ((l & 63) == 0) xr[l >> 6] = v;
+    if ((l & 63) == 0) xr[__builtin_amdgcn_readfirstlane(l >> 6)] = v;  // the wave's slot: a scalar offset
     __syncthreads();
     // one wave value per lane, then a reduction inside each row of 16 lanes
     const int r = group_reduce<NW, IS_MAX>(xr[l & (NW - 1)]);
@@ -2036,8 +2036,10 @@ __global__ __launch_bounds__(crit_reg_wg(N)) void k_crit_reg(const CritRegParams
 // first turn run their stages while the second turn exchanges.  M <-> C
 // crosses waves and runs in two rounds of 2^(n-1) entries, split on entry
 // bit 11, which is register bit 5 in both M and C, so each round empties and
-// refills the same 32 registers.  LDS is 136 / 68 / 34 / 17 KiB for
-// n = 16 / 15 / 14 / 13: 16 waves per CU, <= 128 VGPRs each.
+// refills the same 32 registers.  LDS is 144 / 72 / 36 / 18 KiB for
+// n = 16 / 15 / 14 / 13 (exchange blocks plus the Gray-code walk state):
+// 16 waves per CU, <= 128 VGPRs each, and nothing that can be rebuilt is
+// kept live across the mask loop, so no registers spill.
 // ---------------------------------------------------------------------------
 // Entry of C register jj (bits 0..4 of the register index; bit 5 is the
 // round) without the lane part, with entry bit 11 taken out.
@@ -2059,25 +2061,37 @@ __global__ __launch_bounds__(1 << (N - 6), 4) void k_crit_wide(const CritRegPara
   constexpr int LDS_WORDS = (NB * 64 * ROW > (1 << (N - 1))) ? NB * 64 * ROW : (1 << (N - 1));
   __shared__ __attribute__((aligned(16))) int32_t lds[LDS_WORDS];
   __shared__ int xr[NWAV];
+  // the lane's two bit-sliced words of the current mask (the Gray-code walk
+  // state), kept here rather than in registers: 1 KiB per wave
+  __shared__ uint2 gw[64 * NWAV];
   const int l = threadIdx.x;
   const int w = __builtin_amdgcn_readfirstlane(l >> 6), i = l & 63;  // wave index: uniform, scalar branches
   const bool first_turn = w < NB;
   int32_t* blk = lds + (w % NB) * 64 * ROW;  // this wave's block for A <-> M
-  const int nwords = 1 << (N - 5);
-  const long long kend = 1LL << p.m;
-  const long long kfirst = 1 + (long long)blockIdx.x * p.chunk;
-  const int lw = __builtin_popcount(l);
+  constexpr int nwords = 1 << (N - 5);
+  // 32-bit mask counters (m <= 24): their compares stay on the scalar unit
+  const int kend = 1 << p.m;
+  const int chunk = (int)p.chunk;
+  const int kfirst = 1 + (int)blockIdx.x * chunk;
+  // running aggregates: every value that enters them is uniform, so they
+  // stay in scalar registers (wave 0's copy is the workgroup's)
   int g_nl = 1 << (N - 1), g_unb = 0, g_mw = N + 1, g_ac = 0, g_pw = N + 1;
+  auto words = [&](int b, int lane) {  // bit slice b, the lane's two words
+    return reinterpret_cast<const uint2*>(p.F + b * nwords)[lane];
+  };
 
-  uint32_t G[2], Fn[2] = {0, 0};
-  G[0] = G[1] = 0;
-  if (kfirst < kend) {
-    const long long gk = gray(kfirst);
-    for (int b = 0; b < p.m; ++b)
-      if ((gk >> b) & 1) {
-        G[0] ^= p.F[(long long)b * nwords + 2 * l];
-        G[1] ^= p.F[(long long)b * nwords + 2 * l + 1];
-      }
+  {
+    uint2 G = make_uint2(0, 0);
+    if (kfirst < kend) {
+      const int gk = (int)gray(kfirst);
+      for (int b = 0; b < p.m; ++b)
+        if ((gk >> b) & 1) {
+          const uint2 f = words(b, l);
+          G.x ^= f.x;
+          G.y ^= f.y;
+        }
+    }
+    gw[l] = G;
   }
   // A rows / M words of this wave's block
   auto put_a = [&](const int32_t* v) { put_rows<R, ROW>(blk, i, v); };
@@ -2112,29 +2126,37 @@ __global__ __launch_bounds__(1 << (N - 6), 4) void k_crit_wide(const CritRegPara
     for (int jj = 0; jj < 32; ++jj) v[32 * r + jj] = lds[crit_c_entry<N>(jj) + l];
   };
 
-  for (long long step = 0; step < p.chunk; ++step) {
-    const long long k = kfirst + step;
+  for (int step = 0; step < chunk; ++step) {
+    const int k = kfirst + step;
     const bool valid = k < kend;
-    if (step > 0) {
-      G[0] ^= Fn[0];
-      G[1] ^= Fn[1];
-    }
-    if (k + 1 < kend && step + 1 < p.chunk) {
-      const int b = __builtin_ctzll((unsigned long long)(k + 1));
-      Fn[0] = p.F[(long long)b * nwords + 2 * l];
-      Fn[1] = p.F[(long long)b * nwords + 2 * l + 1];
-    }
+    // the lane index, recomputed per mask: values derived from it (a 64-bit
+    // address, its weight) are cheaper to rebuild than to keep in registers
+    int lr = l;
+    asm volatile("" : "+v"(lr));
     int32_t v[R];
     // ---- first transform: layout A, popcounts (bits 0..4) and bit 5
+    {
+      const uint2 G = gw[lr];
 #pragma unroll
-    for (int t = 0; t < 2; ++t)
+      for (int a = 0; a < 32; ++a) v[a] = (int32_t)__builtin_popcount(G.x ^ walsh_mask(a)) - 16;
 #pragma unroll
-      for (int a = 0; a < 32; ++a) v[t * 32 + a] = (int32_t)__builtin_popcount(G[t] ^ walsh_mask(a)) - 16;
+      for (int a = 0; a < 32; ++a) v[32 + a] = (int32_t)__builtin_popcount(G.y ^ walsh_mask(a)) - 16;
+    }
+    // the next mask's slice: loaded now, folded into gw after the exchange
+    const bool more = k + 1 < kend && step + 1 < chunk;
+    uint2 fn = make_uint2(0, 0);
+    if (more) fn = words(__builtin_ctz((unsigned)(k + 1)), lr);
     reg_stages<R, 5, 6>(v);
     __syncthreads();  // the previous mask's last reads of the blocks are done
     if (first_turn) { put_a(v); wsync(); get_m(v); }
     __syncthreads();
     if (!first_turn) { put_a(v); wsync(); get_m(v); }
+    if (more) {
+      uint2 g = gw[lr];
+      g.x ^= fn.x;
+      g.y ^= fn.y;
+      gw[lr] = g;
+    }
     reg_stages<R, 0, 6>(v);  // M: bits 6..11
     __syncthreads();
     put_m_round(v, 0);
@@ -2145,8 +2167,8 @@ __global__ __launch_bounds__(1 << (N - 6), 4) void k_crit_wide(const CritRegPara
     __syncthreads();
     get_c_round(v, 1);
     reg_stages<R, 17 - N, 5>(v);  // C: bits 12..n-1
-    // u = -W/2 at a = (P(j) << (n-6)) | l
-    const int w0 = -2 * v[0];  // lane 0
+    // u = -W/2 at a = (P(j) << (n-6)) | l; entry 0 is lane 0 of wave 0
+    const int w0 = __builtin_amdgcn_readfirstlane(-2 * v[0]);
     uint32_t ci[7] = {0, 0, 0, 0, 0, 0, 0};
     int mxsq = 0;
 #pragma unroll
@@ -2158,9 +2180,9 @@ __global__ __launch_bounds__(1 << (N - 6), 4) void k_crit_wide(const CritRegPara
     }
     // group results of the first transform now (a convergent reduction the
     // compiler cannot sink past the second transform with all the squares)
-    int mw = first_class<6>(ci, l == 0) + lw;
-    mxsq = crit_group_reduce<64 * NWAV, true>(mxsq, xr, l);
-    mw = crit_group_reduce<64 * NWAV, false>(mw, xr, l);
+    int mw = first_class<6>(ci, l == 0) + __builtin_popcount(lr);
+    mxsq = __builtin_amdgcn_readfirstlane(crit_group_reduce<64 * NWAV, true>(mxsq, xr, l));
+    mw = __builtin_amdgcn_readfirstlane(crit_group_reduce<64 * NWAV, false>(mw, xr, l));
     // ---- second transform: C bits n-6..n-1, M bits 6..n-7, A bits 0..5
     reg_stages<R, 0, 6>(v);
     __syncthreads();
@@ -2187,20 +2209,22 @@ __global__ __launch_bounds__(1 << (N - 6), 4) void k_crit_wide(const CritRegPara
       vmin = min(vmin, v[j]);
       pc[__builtin_popcount(j)] |= (uint32_t)v[j];
     }
-    int pw = first_class<6>(pc, l == 0) + lw;
+    int pw = first_class<6>(pc, l == 0) + __builtin_popcount(lr);
     int ac = max(vmax, -vmin) >> (N - 2);
-    ac = crit_group_reduce<64 * NWAV, true>(ac, xr, l);
-    pw = crit_group_reduce<64 * NWAV, false>(pw, xr, l);
+    ac = __builtin_amdgcn_readfirstlane(crit_group_reduce<64 * NWAV, true>(ac, xr, l));
+    pw = __builtin_amdgcn_readfirstlane(crit_group_reduce<64 * NWAV, false>(pw, xr, l));
     if (mw > N) mw = N + 1;
     if (pw > N) pw = N + 1;
-    if (l == 0 && valid) {
-      const long long b = gray(k);
+    if (valid) {
       const int umax = (int)rintf(sqrtf((float)mxsq));  // mxsq is a perfect square <= 2^30
-      if (p.w0) p.w0[b] = w0;
-      if (p.minwt) p.minwt[b] = mw;
-      if (p.acmax) p.acmax[b] = ac;
-      if (p.pcwt) p.pcwt[b] = pw;
-      g_nl = min(g_nl, (1 << (N - 1)) - umax);
+      if (l == 0) {
+        const int b = (int)gray(k);
+        if (p.w0) p.w0[b] = w0;
+        if (p.minwt) p.minwt[b] = mw;
+        if (p.acmax) p.acmax[b] = ac;
+        if (p.pcwt) p.pcwt[b] = pw;
+      }
+      g_nl = min(g_nl, (1 << (N - 1)) - __builtin_amdgcn_readfirstlane(umax));
       g_unb += w0 != 0;
       g_mw = min(g_mw, mw);
       g_ac = max(g_ac, ac);
