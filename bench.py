@@ -59,9 +59,11 @@ def parse():
     ap.add_argument("--serving-count", type=int, default=2000, help="requests per rate in the sweep")
     ap.add_argument("--extra", action="store_true",  # default unless --quick
                     help="also time the other workloads (8x8, 20x16, 16x20, 12x12 slice, 16x16 spectrum)")
-    ap.add_argument("--variant", type=int, default=0, choices=(0, 1, 2, 3),
+    ap.add_argument("--variant", type=int, default=0, choices=(0, 1, 2, 3, 4),
                     help="butterfly engine for the 16x16 kernel: 0 library default, 1 VALU, 2 matrix cores "
-                         "after popcount stages, 3 fp4 + fp16 matrix-core passes")
+                         "after popcount stages, 3 fp4 + fp16 matrix-core passes; with --batched-only or "
+                         "--extra-only it applies to the batch's plan and the 12x12 fused call, where 4 "
+                         "(int8 + fp16 passes, n = 12 only) is accepted too")
     ap.add_argument("--rounds", type=int, default=0, choices=(0, 4, 8),
                     help="with --variant 3: LDS exchange rounds per mask (0: library default)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -249,18 +251,22 @@ def main():
     if args.copy_calibration:
         copy_calibration(torch)
         return
+    side_tuning = B.sbox_tuning(0, 0, 0, args.variant) if args.variant else None
     if args.batched_only:
         dev = torch.device("cuda:0")
         torch.cuda.set_device(dev)
-        print(json.dumps({"batched": bench_batched(torch, B, inputs, dev, plain_loop=not args.no_plain_loop)}),
-              flush=True)
+        print(json.dumps({"batched": bench_batched(torch, B, inputs, dev, plain_loop=not args.no_plain_loop,
+                                                   tuning=side_tuning)}), flush=True)
         return
     if args.extra_only:
         dev = torch.device("cuda:0")
         torch.cuda.set_device(dev)
         only = tuple(p for p in args.extra_only.split(",") if p)
-        print(json.dumps({"extra": bench_extra(torch, B, inputs, dev, only)}), flush=True)
+        print(json.dumps({"extra": bench_extra(torch, B, inputs, dev, only, tuning12=side_tuning)}), flush=True)
         return
+    if args.variant == 4:
+        raise SystemExit("--variant 4 (int8 first pass) covers n = 12 only: use it with --batched-only or "
+                         "--extra-only 12x12_perm_fused")
     n = m = 16
     w = inputs.workload_16x16()
     S_host = w["perm"]
@@ -388,15 +394,15 @@ def _time_call(torch, fn, reps):
     return a.elapsed_time(b) / reps
 
 
-def bench_extra(torch, B, inputs, dev, only=()):
+def bench_extra(torch, B, inputs, dev, only=(), tuning12=None):
     """The other workloads, timed with HIP events (ms per call); `only`
-    (name prefixes) restricts them."""
+    (name prefixes) restricts them; `tuning12` applies to the 12x12 fused call."""
     out = {}
 
     def want(name):
         return not only or any(name.startswith(p) for p in only)
 
-    def single(S_host, n, m, layout=0, reps=5):
+    def single(S_host, n, m, layout=0, reps=5, tuning=None):
         S = B.table_to_device(S_host, m, device=dev)
         nl = torch.empty(1, dtype=torch.int32, device=dev)
         mx = torch.empty(1 << m, dtype=torch.int32, device=dev)
@@ -407,7 +413,7 @@ def bench_extra(torch, B, inputs, dev, only=()):
         def call():
             st = B.sbox_walsh_nl_ex(S.data_ptr(), n, m, S.element_size(), mx.data_ptr(), nl.data_ptr(),
                                     spec.data_ptr() if spec is not None else 0, layout, ws.ptr, ws.nbytes,
-                                    None, sptr)
+                                    tuning, sptr)
             if st != 0:
                 raise RuntimeError(B.last_error())
         ms = _time_call(torch, call, reps)
@@ -440,7 +446,11 @@ def bench_extra(torch, B, inputs, dev, only=()):
                ("8x8_perm_spectrum_b", lambda: single(w8["perm"], 8, 8, 1, reps=50)),
                ("8x8_perm_spectrum_a", lambda: single(w8["perm"], 8, 8, 2, reps=50)),
                ("12x12_perm_fused", lambda: single(inputs.permutation(12, inputs.rng(inputs.SEED_BASE + 6)), 12, 12,
-                                                   reps=50)),
+                                                   reps=50, tuning=tuning12)),
+               # n = 12 engine comparison at scale (2^20 masks): the fp4 (default) or, with
+               # --variant 4, the int8 first pass
+               ("12x20_fused", lambda: single(inputs.random_function(12, 20, inputs.rng(inputs.SEED_BASE + 11)), 12,
+                                              20, reps=10, tuning=tuning12)),
                ("16x20_fused", lambda: single(ns["s16x20"], 16, 20, reps=2)),
                ("20x16_fused", lambda: single(ns["s20x16"], 20, 16, reps=1)),
                ("12x12_slice_spectrum_a", lambda: single(ns["slice12"], 12, 12, 2, reps=10)),
@@ -517,13 +527,13 @@ def bench_extra(torch, B, inputs, dev, only=()):
     return out
 
 
-def bench_batched(torch, B, inputs, dev, reps=5, plain_loop=True):
+def bench_batched(torch, B, inputs, dev, reps=5, plain_loop=True, tuning=None):
     """4096 mixed boxes (n = m in {6,8,10,12}): one planned batched launch vs a
     loop of single-box calls on one stream."""
     batch = inputs.workload_batched()
     tabs = [B.table_to_device(S, n, device=dev) for n, S in batch]
     ns = [n for n, _ in batch]
-    plan = B.Plan(tabs, ns, ns)
+    plan = B.Plan(tabs, ns, ns, tuning=tuning)
     stream = torch.cuda.current_stream(dev)
     plan.launch()
     torch.cuda.synchronize(dev)

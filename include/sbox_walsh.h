@@ -85,8 +85,11 @@ typedef enum {
  *             operands taken straight from the table's bits, then fp16
  *             passes (two at n = 16, where split_p = 4 or 8 picks the LDS
  *             exchange rounds; one at n = 12, one wave per mask); exact.
- *             Other sizes and modes accept 0 or 1 only.  Batched launches
- *             and plans apply it to their n = 12 and n = 16 boxes.
+ *             4 (n = 12 only) as 3 with the first pass on int8 operands
+ *             (int32 accumulation), kept for comparison: it issues twice the
+ *             matrix-core work of 3.  Other sizes and modes accept 0 or 1
+ *             only.  Batched launches and plans apply it to their n = 12
+ *             and n = 16 boxes (variant 4 runs n = 16 boxes as 3).
  */
 typedef struct sbox_tuning {
     int32_t split_p;

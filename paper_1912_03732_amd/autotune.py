@@ -45,13 +45,17 @@ def candidates(n: int, m: int, cus: int = 256) -> List[Tuple[int, int, int]]:
         for c in chunks:
             for g in grids:
                 out.append((p if n > 8 else 0, c, g, 1 if n in (12, 16) else 0))
-    if n in (12, 16):  # the matrix-core engines (at n = 16 also fp4 + fp16 with 4 or 8 exchange rounds)
+    if n in (12, 16):  # the matrix-core engines: fp16 (2), fp4 + fp16 (3; at n = 16 with 4 or 8
+        # exchange rounds), at n = 12 also int8 + fp16 (4)
         for c in chunks:
             for g in grids:
                 out.append((0, c, g, 2))
                 if n == 16:
                     for r in (4, 8):
                         out.append((r, c, g, 3))
+                else:
+                    out.append((0, c, g, 3))
+                    out.append((0, c, g, 4))
     return out
 
 

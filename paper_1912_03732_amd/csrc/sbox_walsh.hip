@@ -209,10 +209,10 @@ long long inverse_gray(long long j) {
 }
 
 // Butterfly engine of the n = 12 and n = 16 fused maximum: the library
-// default is variant 3, which at n = 16 runs the fp4 + fp16 matrix-core
-// kernel and at n = 12 the matrix-core kernel of variant 2; variant 2 at
-// n = 16 is the matrix-core kernel after popcount stages, variant 1 the
-// packed 16-bit VALU one.
+// default is variant 3, the fp4 + fp16 matrix-core kernels; variant 2 the
+// fp16 matrix-core kernels after popcount stages, variant 1 the packed
+// 16-bit VALU ones, variant 4 (n = 12) an int8 first pass in place of the
+// fp4 one (plans run their n = 16 boxes on variant 3 then).
 constexpr int kDefaultVariant = 3;
 // LDS exchange rounds of the n = 16 matrix-core kernel (2: 64 KiB, 4: 32 KiB per workgroup)
 #ifndef SBW_MFMA_ROUNDS
@@ -228,10 +228,11 @@ bool use_mfma(int n, const sbox_tuning* tun) { return mfma_n(n) && variant_of(tu
 #define SBW_MX_ROUNDS 4
 #endif
 // The n = 12 fp4 engine reads sparse words (kWordsFp4).
-bool fp4_words(int n, const sbox_tuning* tun) { return n == 12 && use_mfma(n, tun) && variant_of(tun) == 3; }
+// The int8 engine (variant 4) reads the same words.
+bool fp4_words(int n, const sbox_tuning* tun) { return n == 12 && use_mfma(n, tun) && variant_of(tun) >= 3; }
 KFn mfma_kernel(int n, const sbox_tuning* tun) {
-  if (n == 12) return variant_of(tun) == 3 ? &k_walsh_mx12 : &k_walsh_mfma12;
-  if (variant_of(tun) != 3) return &k_walsh_mfma16<kMfmaRounds>;
+  if (n == 12) return variant_of(tun) == 4 ? &k_walsh_i8x12 : variant_of(tun) == 3 ? &k_walsh_mx12 : &k_walsh_mfma12;
+  if (variant_of(tun) == 2) return &k_walsh_mfma16<kMfmaRounds>;
   const int rounds = (tun && tun->split_p) ? tun->split_p : SBW_MX_ROUNDS;
   return rounds == 8 ? &k_walsh_mx16<1> : &k_walsh_mx16<2>;
 }
@@ -915,12 +916,14 @@ sbox_status sbox_walsh_nl_ex(const void* S, int n, int m, int s_elem_bytes, int3
   if (tuning) {
     if (tuning->chunk < 0 || tuning->grid < 0 || tuning->split_p < 0)
       return fail(SBOX_ERR_INVALID_ARG, "negative tuning field");
-    if (tuning->variant < 0 || tuning->variant > 3)
-      return fail(SBOX_ERR_INVALID_ARG, "tuning variant %d (0, 1, 2 or 3)", tuning->variant);
+    if (tuning->variant < 0 || tuning->variant > 4)
+      return fail(SBOX_ERR_INVALID_ARG, "tuning variant %d (0 to 4)", tuning->variant);
     if (tuning->variant == 2 && !(mfma_n(n) && layout == 0))
       return fail(SBOX_ERR_INVALID_ARG, "the matrix-core variant covers n = 12 and 16 without a spectrum only");
     if (tuning->variant == 3 && !(mfma_n(n) && layout == 0))
       return fail(SBOX_ERR_INVALID_ARG, "the fp4 matrix-core variant covers n = 12 and 16 without a spectrum only");
+    if (tuning->variant == 4 && !(n == 12 && layout == 0))
+      return fail(SBOX_ERR_INVALID_ARG, "the int8 matrix-core variant covers n = 12 without a spectrum only");
     if (tuning->variant == 3 && n == 16 && tuning->split_p && tuning->split_p != 4 && tuning->split_p != 8)
       return fail(SBOX_ERR_INVALID_ARG, "the fp4 matrix-core variant takes split_p = 4 or 8 exchange rounds");
     if (tuning->split_p && n > 8 && n <= 16 && !(tuning->variant >= 2 && mfma_n(n) && layout == 0) &&
@@ -1324,8 +1327,8 @@ sbox_status sbox_plan_create(const sbox_job* jobs, int32_t count, const sbox_tun
   *out = nullptr;
   if (tuning && (tuning->chunk < 0 || tuning->grid < 0 || tuning->split_p < 0))
     return fail(SBOX_ERR_INVALID_ARG, "negative tuning field");
-  if (tuning && (tuning->variant < 0 || tuning->variant > 3))
-    return fail(SBOX_ERR_INVALID_ARG, "tuning variant %d (0, 1, 2 or 3)", tuning->variant);
+  if (tuning && (tuning->variant < 0 || tuning->variant > 4))
+    return fail(SBOX_ERR_INVALID_ARG, "tuning variant %d (0 to 4)", tuning->variant);
   sbox_plan* p = new sbox_plan();
   sbox_status s = plan_batch(jobs, count, tuning, &p->layout);
   if (s) {

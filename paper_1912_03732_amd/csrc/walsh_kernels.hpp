@@ -1366,6 +1366,156 @@ __global__ __launch_bounds__(kWG, 5) void k_walsh_mx12(const KParams kp) {
 }
 
 // ---------------------------------------------------------------------------
+// n = 12, max mode, the same two passes with the first on int8 operands
+// (v_mfma_i32_16x16x64_i8, int32 accumulation), over the same sparse words.
+// An operand byte must hold the bit itself (0 or 1), so each of the four
+// nibble bits of a byte (x0, x1) gives its own operand, (G >> (1 + x0 +
+// 4 x1)) & 0x01010101, whose K slots are (x2, x3 | x4, x5 | x10, x11): the
+// byte, the register and the lane group.  x1 is transformed by accumulating
+// its two products, the second against B with the sign of column bit 0
+// flipped; x0 stays for pass 2 as in k_walsh_mx12, so the pass-1 outputs
+// (same columns, |value| <= 64) and pass 2 are unchanged.  Per mask that is
+// 32 int8 products of K = 64 where k_walsh_mx12 issues 16 fp4 products of
+// K = 128 at the same 16 cycles each, and four times the operand
+// extraction; kept as an alternative engine for the comparison.
+// ---------------------------------------------------------------------------
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint32_t i8_sign_word(int kbase, int a) {
+  // int8 +1 (0x01) or -1 (0xFF) for the 4 bytes k = kbase + byte against output a
+  uint32_t w = 0;
+#pragma unroll
+  for (int byte = 0; byte < 4; ++byte) w |= ((__builtin_popcount((kbase + byte) & a) & 1) ? 0xFFu : 0x01u) << (8 * byte);
+  return w;
+}
+
+__global__ __launch_bounds__(kWG, 4) void k_walsh_i8x12(const KParams kp) {
+  constexpr int NW = 4;
+  constexpr int GPW = kWG / 64;  // masks (waves) per workgroup
+  constexpr uint32_t kFlip = 0xFEFEFEFEu;  // +1 <-> -1 in every byte
+  __shared__ long long s_item;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int C = kp.chunk;
+  const int col = lane & 15, g = lane >> 4;
+
+  // B for x1 = 0: the K slots (byte, register) against pass-1 output bits
+  // 1..4 (col >> 1, column-block bit 0); the lane group against column-block
+  // bits 1, 2 is a whole-word flip, and x1 = 1 flips by column bit 0.
+  uint32_t Bb[2][4];
+#pragma unroll
+  for (int c0 = 0; c0 < 2; ++c0)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Bb[c0][r] = i8_sign_word(4 * r, (16 * c0 + col) >> 1);
+  uint32_t gflip[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) gflip[c] = (__builtin_popcount(g & c) & 1) ? kFlip : 0u;
+  const uint32_t x1flip = (col & 1) ? kFlip : 0u;
+  f16x8 hb0, hb1;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int kappa = j + 8 * g;
+    hb0[j] = hsign(kappa & col);
+    hb1[j] = hsign(kappa & (col + 16));
+  }
+  const int ifix = col == 0 ? -64 : 0;
+  const i32x4 cfix = {ifix, ifix, ifix, ifix};
+  const i32x4 izero = {0, 0, 0, 0};
+  const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+
+  for (;;) {
+    if (tid == 0) s_item = (long long)atomicAdd(kp.queue, 1);
+    __syncthreads();
+    const long long item = __builtin_amdgcn_readfirstlane((int)s_item);
+    __syncthreads();
+    if (item >= kp.total_items) break;
+    JobDesc jd;
+    long long li;
+    if (kp.jobs == nullptr) {
+      jd = kp.job0;
+      li = item;
+    } else {
+      int lo = 0, hi = kp.njobs - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (kp.jobs[mid].item_begin <= item) lo = mid; else hi = mid - 1;
+      }
+      jd = kp.jobs[lo];
+      li = item - jd.item_begin;
+    }
+    const long long kfirst = (li * GPW + wave) * (long long)C;
+    const long long kend = 1LL << jd.m;
+    const long long wb = (long long)lane * NW;
+    const int n = jd.n;
+    int runmin = 0x7fffffff;
+    uint32_t G[NW], Fn[NW];
+
+    for (int step = 0; step < C; ++step) {
+      const long long k = kfirst + step;
+      if (k >= kend) break;  // wave-uniform
+      if (step == 0) {
+#pragma unroll
+        for (int w = 0; w < NW; ++w) G[w] = 0;
+        const long long gk = gray(k);
+        for (int i = 0; i < jd.m; ++i)
+          if ((gk >> i) & 1) load_words<NW>(G, jd.F + (long long)i * jd.nwords + wb, true);
+      } else {
+#pragma unroll
+        for (int w = 0; w < NW; ++w) G[w] ^= Fn[w];
+      }
+      if (step + 1 < C && k + 1 < kend) {
+        const int i = __builtin_ctzll((unsigned long long)(k + 1));
+        load_words<NW>(Fn, jd.F + (long long)i * jd.nwords + wb, false);
+      }
+      // the x1 flip, opaque per mask: the x1 = 1 operands are rebuilt per
+      // mask rather than all 32 of them kept live across the loop
+      uint32_t xf = x1flip;
+      asm volatile("" : "+v"(xf));
+      // A[x0][x1]: the bit at nibble position 1 + x0 of nibble x1 of every byte
+      i32x4 A[2][2];
+#pragma unroll
+      for (int x0 = 0; x0 < 2; ++x0)
+#pragma unroll
+        for (int x1 = 0; x1 < 2; ++x1)
+#pragma unroll
+          for (int r = 0; r < NW; ++r) A[x0][x1][r] = (int)((G[r] >> (1 + x0 + 4 * x1)) & 0x01010101u);
+      float m0 = 0.0f, m1 = 0.0f;
+#pragma unroll
+      for (int cb = 0; cb < 8; ++cb) {
+        const uint32_t fl = gflip[cb >> 1];
+        i32x4 b0, b1;
+#pragma unroll
+        for (int r = 0; r < NW; ++r) {
+          b0[r] = (int)(Bb[cb & 1][r] ^ fl);
+          b1[r] = (int)(Bb[cb & 1][r] ^ fl ^ xf);
+        }
+        const i32x4 c = cb == 0 ? cfix : izero;
+        const i32x4 d0 = __builtin_amdgcn_mfma_i32_16x16x64_i8(
+            A[0][1], b1, __builtin_amdgcn_mfma_i32_16x16x64_i8(A[0][0], b0, c, 0, 0, 0), 0, 0, 0);
+        const i32x4 d1 = __builtin_amdgcn_mfma_i32_16x16x64_i8(
+            A[1][1], b1, __builtin_amdgcn_mfma_i32_16x16x64_i8(A[1][0], b0, c, 0, 0, 0), 0, 0, 0);
+        const f16x8 av = as_f16x8(pk_cvt_f16((float)d0[0], (float)d1[0]), pk_cvt_f16((float)d0[1], (float)d1[1]),
+                                  pk_cvt_f16((float)d0[2], (float)d1[2]), pk_cvt_f16((float)d0[3], (float)d1[3]));
+        const f32x4 e0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(av, hb0, zero, 0, 0, 0);
+        const f32x4 e1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(av, hb1, zero, 0, 0, 0);
+        m0 = fmaxf(fmaxf(m0, fabsf(e0[0])), fabsf(e1[0]));
+        m1 = fmaxf(fmaxf(m1, fabsf(e0[1])), fabsf(e1[1]));
+        m0 = fmaxf(fmaxf(m0, fabsf(e0[2])), fabsf(e1[2]));
+        m1 = fmaxf(fmaxf(m1, fabsf(e0[3])), fabsf(e1[3]));
+      }
+      const int mx = wave_max((int)fmaxf(m0, m1));
+      if (lane == 0 && k != 0) {
+        if (jd.maxabs) jd.maxabs[(uint32_t)gray(k)] = 2 * mx;
+        runmin = min(runmin, (1 << (n - 1)) - mx);
+      }
+    }
+    if (lane == 0 && runmin != 0x7fffffff) atomicMin(jd.nl, runmin);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // n = 16 + L, 1 <= L <= 4, max mode: recompute instead of materialising.
 //
 // Write x = (x_hi : L bits, x_lo : 16 bits).  For a fixed high output index

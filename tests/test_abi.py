@@ -70,7 +70,10 @@ def test_large_n_workspace_grows_with_n(lib):
     (dict(n=12, tuning=B.sbox_tuning(5, 0, 0, 0)), B.SBOX_ERR_INVALID_ARG),
     (dict(n=16, tuning=B.sbox_tuning(7, 0, 0, 0)), B.SBOX_ERR_INVALID_ARG),
     (dict(tuning=B.sbox_tuning(0, -1, 0, 0)), B.SBOX_ERR_INVALID_ARG),
+    (dict(tuning=B.sbox_tuning(0, 0, 0, 5)), B.SBOX_ERR_INVALID_ARG),
     (dict(tuning=B.sbox_tuning(0, 0, 0, 4)), B.SBOX_ERR_INVALID_ARG),
+    (dict(n=16, m=16, tuning=B.sbox_tuning(0, 0, 0, 4)), B.SBOX_ERR_INVALID_ARG),
+    (dict(n=12, m=12, layout=1, spec=4096, tuning=B.sbox_tuning(0, 0, 0, 4)), B.SBOX_ERR_INVALID_ARG),
     (dict(n=13, tuning=B.sbox_tuning(0, 0, 0, 3)), B.SBOX_ERR_INVALID_ARG),
     (dict(n=12, m=12, layout=1, spec=4096, tuning=B.sbox_tuning(0, 0, 0, 3)), B.SBOX_ERR_INVALID_ARG),
     (dict(n=16, m=8, tuning=B.sbox_tuning(6, 0, 0, 3)), B.SBOX_ERR_INVALID_ARG),

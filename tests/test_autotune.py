@@ -28,7 +28,8 @@ def test_candidates_cover_chunks_and_grids():
     assert {p for p, _, _, v in c16 if v == 1} == {8} and {g for _, _, g, _ in c16} == {0}
     assert {v for _, _, _, v in c16} == {1, 2, 3}
     assert {p for p, _, _, v in c16 if v == 3} == {4, 8}  # the fp4 engine's exchange rounds
-    assert 3 not in {v for _, _, _, v in c}
+    assert {v for _, _, _, v in c} == {1, 2, 3, 4}  # at n = 12 also the fp4 and int8 first passes
+    assert {p for p, _, _, v in c if v >= 2} == {0}
     assert {p for p, _, _, _ in autotune.candidates(7, 7)} == {0}
 
 

@@ -506,20 +506,22 @@ def test_fp4_matrix_core_launch_shapes(chunk, grid, rounds):
     check_against_oracle(S, 16, 10, nthreads=NT, tuning=B.sbox_tuning(rounds, chunk, grid, 3))
 
 
-def test_fp4_matrix_core_in_a_plan():
-    """Variant 3 inside a batched plan with n = 12 and other boxes."""
+@pytest.mark.parametrize("variant", [3, 4])
+def test_fp4_matrix_core_in_a_plan(variant):
+    """Variants 3 and 4 inside a batched plan with n = 12 and other boxes
+    (variant 4 runs the n = 16 boxes on variant 3's engine)."""
     import torch
     g = inputs.rng(15700)
     boxes = [(16, 16, inputs.permutation(16, g)), (16, 5, inputs.random_function(16, 5, g)),
              (12, 12, inputs.permutation(12, g)), (8, 8, inputs.permutation(8, g))]
     tabs = [dev_table(S, m) for n, m, S in boxes]
-    plan = B.Plan(tabs, [b[0] for b in boxes], [b[1] for b in boxes], tuning=B.sbox_tuning(0, 0, 0, 3))
+    plan = B.Plan(tabs, [b[0] for b in boxes], [b[1] for b in boxes], tuning=B.sbox_tuning(0, 0, 0, variant))
     plan.launch()
     torch.cuda.synchronize()
     nl = plan.nl.cpu().numpy()
     for i, (n, m, S) in enumerate(boxes):
         onl, omx = oracle.walsh_nl(S, n, m, nthreads=NT)
-        assert nl[i] == onl and np.array_equal(plan.maxabs[i].cpu().numpy(), omx), (i, n, m)
+        assert nl[i] == onl and np.array_equal(plan.maxabs[i].cpu().numpy(), omx), (variant, i, n, m)
     plan.close()
 
 
@@ -562,11 +564,13 @@ def test_a_major_slabs_graph_replay():
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("variant", [3, 4])
 @pytest.mark.parametrize("m,kind", [(1, "random"), (5, "random"), (12, "perm"), (12, "inv"), (12, "const"),
                                     (12, "affine"), (12, "zero"), (17, "random"), (20, "random")])
-def test_fp4_matrix_core_variant_12(m, kind):
-    """n = 12 on two matrix-core passes (fp4 on sparse words, then fp16; one
-    wave per mask), bit-exact; structured boxes reach |W| = 2^12."""
+def test_fp4_matrix_core_variant_12(m, kind, variant):
+    """n = 12 on two matrix-core passes (fp4, variant 3, or int8, variant 4,
+    on sparse words, then fp16; one wave per mask), bit-exact; structured
+    boxes reach |W| = 2^12."""
     if kind == "perm":
         S = inputs.permutation(12, inputs.rng(6101))
     elif kind == "inv":
@@ -580,14 +584,15 @@ def test_fp4_matrix_core_variant_12(m, kind):
         S = np.zeros(1 << 12, np.uint16)
     else:
         S = table(12, m, 16500 + m)
-    nl, mx = check_against_oracle(S, 12, m, nthreads=NT, tuning=B.sbox_tuning(0, 0, 0, 3))
+    nl, mx = check_against_oracle(S, 12, m, nthreads=NT, tuning=B.sbox_tuning(0, 0, 0, variant))
     if kind == "inv":
         assert nl == (1 << 11) - (1 << 6)
     if kind in ("const", "affine", "zero"):
         assert nl == 0
 
 
+@pytest.mark.parametrize("variant", [3, 4])
 @pytest.mark.parametrize("chunk,grid", [(1, 1), (3, 7), (64, 0), (9, 1000)])
-def test_fp4_matrix_core_12_launch_shapes(chunk, grid):
+def test_fp4_matrix_core_12_launch_shapes(chunk, grid, variant):
     S = table(12, 11, 16600 + chunk)
-    check_against_oracle(S, 12, 11, nthreads=NT, tuning=B.sbox_tuning(0, chunk, grid, 3))
+    check_against_oracle(S, 12, 11, nthreads=NT, tuning=B.sbox_tuning(0, chunk, grid, variant))

@@ -74,11 +74,11 @@ def test_batched_workload_4096_graph_replay_vs_oracle():
     plan.close()
 
 
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1, 4])
 def test_batched_long_items_every_engine(variant):
     """Classes of >= 32 boxes at n = 9, 10, 11, 12 (ragged m, so items cover
-    partial boxes too), with the default engines (matrix cores at n = 12) or
-    the VALU kernels everywhere."""
+    partial boxes too), with the default engines (matrix cores at n = 12),
+    the VALU kernels everywhere, or the int8 first pass at n = 12."""
     g = inputs.rng(10701 + variant)
     boxes = []
     for n, count in ((12, 72), (11, 33), (10, 40), (9, 32), (6, 5)):
