@@ -380,9 +380,16 @@ def copy_calibration(torch, nbytes=1 << 30, reps=3):
     print(json.dumps({"copy_bytes": nbytes, "reps": reps}), flush=True)
 
 
-def _time_call(torch, fn, reps):
+def _time_call(torch, fn, reps, warm_ms=30.0):
+    """Mean ms per call over `reps` calls, after at least `warm_ms` of
+    untimed calls (the clocks ramp up over tens of milliseconds)."""
     fn()
     torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while (time.perf_counter() - t0) * 1e3 < warm_ms:
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
     s = torch.cuda.current_stream()
     a = torch.cuda.Event(enable_timing=True)
     b = torch.cuda.Event(enable_timing=True)
@@ -542,6 +549,10 @@ def bench_batched(torch, B, inputs, dev, reps=5, plain_loop=True, tuning=None):
         plan.launch()
     g.replay()
     torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()  # untimed replays for at least 30 ms: the clocks ramp up first
+    while time.perf_counter() - t0 < 0.03:
+        g.replay()
+        torch.cuda.synchronize(dev)
     t0 = time.perf_counter()
     for _ in range(reps):
         g.replay()

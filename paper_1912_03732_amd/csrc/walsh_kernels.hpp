@@ -1258,7 +1258,7 @@ __global__ __launch_bounds__(kWG, 4) void k_walsh_mfma12(const KParams kp) {
 //   3. The maximum of |V| with abs modifiers.
 // Every bit of x is transformed once (7 + 5).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kWG, 5) void k_walsh_mx12(const KParams kp) {
+__global__ __launch_bounds__(kWG, 3) void k_walsh_mx12(const KParams kp) {
   constexpr int NW = 4;
   constexpr int GPW = kWG / 64;  // masks (waves) per workgroup
   __shared__ long long s_item;
@@ -1336,18 +1336,24 @@ __global__ __launch_bounds__(kWG, 5) void k_walsh_mx12(const KParams kp) {
                         (int)(G[3] & 0x22222222u), 0, 0, 0, 0};
       const i32x8 a1 = {(int)(G[0] & 0x44444444u), (int)(G[1] & 0x44444444u), (int)(G[2] & 0x44444444u),
                         (int)(G[3] & 0x44444444u), 0, 0, 0, 0};
+      // all 16 first-pass products first, then the casts and second-pass
+      // products: each cast waits on a product issued long before, and the
+      // wave keeps the matrix cores busy on its own (132 registers, three
+      // waves a SIMD, measured faster than five waves interleaving the passes)
       float m0 = 0.0f, m1 = 0.0f;
+      f32x4 d0[8], d1[8];
 #pragma unroll
       for (int cb = 0; cb < 8; ++cb) {
         const uint32_t fl = gflip[cb >> 1];
         const i32x8 b = {(int)(B1b[cb & 1][0] ^ fl), (int)(B1b[cb & 1][1] ^ fl), (int)(B1b[cb & 1][2] ^ fl),
                          (int)(B1b[cb & 1][3] ^ fl), 0, 0, 0, 0};
-        const f32x4 d0 = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a0, b, cb == 0 ? cfix : zero, 4, 4, 0,
-                                                                          127, 0, 127);
-        const f32x4 d1 = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a1, b, cb == 0 ? cfix : zero, 4, 4, 0,
-                                                                          126, 0, 127);
-        const f16x8 av = as_f16x8(pk_cvt_f16(d0[0], d1[0]), pk_cvt_f16(d0[1], d1[1]), pk_cvt_f16(d0[2], d1[2]),
-                                  pk_cvt_f16(d0[3], d1[3]));
+        d0[cb] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a0, b, cb == 0 ? cfix : zero, 4, 4, 0, 127, 0, 127);
+        d1[cb] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a1, b, cb == 0 ? cfix : zero, 4, 4, 0, 126, 0, 127);
+      }
+#pragma unroll
+      for (int cb = 0; cb < 8; ++cb) {
+        const f16x8 av = as_f16x8(pk_cvt_f16(d0[cb][0], d1[cb][0]), pk_cvt_f16(d0[cb][1], d1[cb][1]),
+                                  pk_cvt_f16(d0[cb][2], d1[cb][2]), pk_cvt_f16(d0[cb][3], d1[cb][3]));
         const f32x4 e0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(av, hb0, zero, 0, 0, 0);
         const f32x4 e1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(av, hb1, zero, 0, 0, 0);
         m0 = fmaxf(fmaxf(m0, fabsf(e0[0])), fabsf(e1[0]));
@@ -1389,7 +1395,7 @@ __device__ __forceinline__ uint32_t i8_sign_word(int kbase, int a) {
   return w;
 }
 
-__global__ __launch_bounds__(kWG, 4) void k_walsh_i8x12(const KParams kp) {
+__global__ __launch_bounds__(kWG, 3) void k_walsh_i8x12(const KParams kp) {
   constexpr int NW = 4;
   constexpr int GPW = kWG / 64;  // masks (waves) per workgroup
   constexpr uint32_t kFlip = 0xFEFEFEFEu;  // +1 <-> -1 in every byte
@@ -1481,7 +1487,9 @@ __global__ __launch_bounds__(kWG, 4) void k_walsh_i8x12(const KParams kp) {
         for (int x1 = 0; x1 < 2; ++x1)
 #pragma unroll
           for (int r = 0; r < NW; ++r) A[x0][x1][r] = (int)((G[r] >> (1 + x0 + 4 * x1)) & 0x01010101u);
+      // all first-pass products first, then the casts and second-pass products
       float m0 = 0.0f, m1 = 0.0f;
+      i32x4 d0[8], d1[8];
 #pragma unroll
       for (int cb = 0; cb < 8; ++cb) {
         const uint32_t fl = gflip[cb >> 1];
@@ -1492,12 +1500,17 @@ __global__ __launch_bounds__(kWG, 4) void k_walsh_i8x12(const KParams kp) {
           b1[r] = (int)(Bb[cb & 1][r] ^ fl ^ xf);
         }
         const i32x4 c = cb == 0 ? cfix : izero;
-        const i32x4 d0 = __builtin_amdgcn_mfma_i32_16x16x64_i8(
+        d0[cb] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
             A[0][1], b1, __builtin_amdgcn_mfma_i32_16x16x64_i8(A[0][0], b0, c, 0, 0, 0), 0, 0, 0);
-        const i32x4 d1 = __builtin_amdgcn_mfma_i32_16x16x64_i8(
+        d1[cb] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
             A[1][1], b1, __builtin_amdgcn_mfma_i32_16x16x64_i8(A[1][0], b0, c, 0, 0, 0), 0, 0, 0);
-        const f16x8 av = as_f16x8(pk_cvt_f16((float)d0[0], (float)d1[0]), pk_cvt_f16((float)d0[1], (float)d1[1]),
-                                  pk_cvt_f16((float)d0[2], (float)d1[2]), pk_cvt_f16((float)d0[3], (float)d1[3]));
+      }
+#pragma unroll
+      for (int cb = 0; cb < 8; ++cb) {
+        const f16x8 av = as_f16x8(pk_cvt_f16((float)d0[cb][0], (float)d1[cb][0]),
+                                  pk_cvt_f16((float)d0[cb][1], (float)d1[cb][1]),
+                                  pk_cvt_f16((float)d0[cb][2], (float)d1[cb][2]),
+                                  pk_cvt_f16((float)d0[cb][3], (float)d1[cb][3]));
         const f32x4 e0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(av, hb0, zero, 0, 0, 0);
         const f32x4 e1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(av, hb1, zero, 0, 0, 0);
         m0 = fmaxf(fmaxf(m0, fabsf(e0[0])), fabsf(e1[0]));
