@@ -1375,9 +1375,9 @@ __global__ __launch_bounds__(kWG, 3) void k_walsh_mx12(const KParams kp) {
 // n = 12, max mode, the same two passes with the first on int8 operands
 // (v_mfma_i32_16x16x64_i8, int32 accumulation), over the same sparse words.
 // An operand byte must hold the bit itself (0 or 1), so each of the four
-// nibble bits of a byte (x0, x1) gives its own operand, (G >> (1 + x0 +
-// 4 x1)) & 0x01010101, whose K slots are (x2, x3 | x4, x5 | x10, x11): the
-// byte, the register and the lane group.  x1 is transformed by accumulating
+// bits of a byte that hold x values (bits 1, 2, 5, 6: x0, x1) gives its own
+// operand, (G >> (1 + x0 + 4 x1)) & 0x01010101, whose K slots are (x2, x3 |
+// x4, x5 | x10, x11): the byte, the register and the lane group.  x1 is transformed by accumulating
 // its two products, the second against B with the sign of column bit 0
 // flipped; x0 stays for pass 2 as in k_walsh_mx12, so the pass-1 outputs
 // (same columns, |value| <= 64) and pass 2 are unchanged.  Per mask that is
