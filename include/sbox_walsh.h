@@ -273,7 +273,8 @@ size_t sbox_criteria_workspace_bytes(int n, int m);
  *                 fused per-mask maximum and NL of the same pass.
  *   workspace     at least sbox_walsh_histogram_workspace_bytes(n, m) bytes.
  * Limits: 1 <= n <= 16, 1 <= m <= 24.  No allocation, no host
- * synchronisation.  About as costly as a spectrum pass without its stores.
+ * synchronisation.  Costs the fused transform plus one LDS atomic per
+ * coefficient (at n = 16 about three times the fused NL call).
  */
 sbox_status sbox_walsh_histogram(const void* S, int n, int m, int s_elem_bytes, uint64_t* hist,
                                  int32_t* maxabs_per_b, int32_t* nl, void* workspace,

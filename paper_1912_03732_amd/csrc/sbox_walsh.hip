@@ -426,6 +426,44 @@ sbox_status run_single(const void* S, int n, int m, int eb, int32_t* maxabs, int
     return SBOX_OK;
   }
 
+  if (layout == 0 && hist && n == 16 && use_mfma(n, tun)) {
+    // |W| histogram at n = 16 on the fp4 + fp16 matrix-core transform (LDS
+    // bins below kMxHistBins - 1), then the large-value pass for the rest.
+    // Eight exchange rounds: with four, the counting spills registers.
+    const void* fn = (const void*)&k_walsh_mx16<1, true>;
+    int occ = 1;
+    s = occupancy(fn, &occ);
+    if (s) return s;
+    const long long M = 1LL << m;
+    const int grid_cap = (tun && tun->grid) ? tun->grid : occ * cus;
+    int chunk = 1;
+    pick_chunk(M, mfma_groups(n), grid_cap, tun ? tun->chunk : 0, &chunk);
+    KParams kp{};
+    kp.job0 = jd;
+    kp.njobs = 1;
+    kp.chunk = chunk;
+    kp.queue = queue;
+    kp.total_items = (M + chunk - 1) / chunk;
+    kp.hist = hist;
+    kp.hist_over = hist_over;
+    const int grid = (int)std::min<long long>(grid_cap, kp.total_items);
+    void* args[] = {&kp};
+    s = launch(fn, dim3(grid), dim3(kWG), args, st);
+    if (s) return s;
+    // the VALU kernel's large-value pass: one thread group per workgroup at
+    // n = 16 as well, so the same items cover the same masks
+    KFn fnb = lookup_kernel(16, 8, kHistBig);
+    if (!fnb) return fail(SBOX_ERR_INVALID_ARG, "no histogram kernel for n=16");
+    int occb = 1;
+    s = occupancy((const void*)fnb, &occb);
+    if (s) return s;
+    kp.queue = queue + 1;
+    kp.hist_cut = kMxHistBins - 1;
+    const int gridb = (int)std::min<long long>((long long)occb * cus, kp.total_items);
+    void* argsb[] = {&kp};
+    return launch((const void*)fnb, dim3(gridb), dim3(kWG), argsb, st);
+  }
+
   if (layout == 0 && !hist && use_mfma(n, tun)) {
     const void* fn = (const void*)mfma_kernel(n, tun);
     int occ = 1;
@@ -484,6 +522,7 @@ sbox_status run_single(const void* S, int n, int m, int eb, int32_t* maxabs, int
     s = occupancy((const void*)fnb, &occb);
     if (s) return s;
     kp.queue = queue + 1;
+    kp.hist_cut = kHistBins - 1;
     const int gridb = (int)std::min<long long>((long long)occb * cus, kp.total_items);
     void* argsb[] = {&kp};
     return launch((const void*)fnb, dim3(gridb), dim3(kWG), argsb, st);

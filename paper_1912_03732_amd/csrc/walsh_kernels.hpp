@@ -89,10 +89,11 @@ struct KParams {
   long long kbase;       // first Gray index of this batch of masks
   long long kcount;      // masks in this batch (0: all 2^m masks, block mode: required)
   int nblk_log;          // n - 16
+  int hist_cut;          // large-value pass: adds the values with |W|/2 >= hist_cut
   long long row0;        // b-major store mode: row b goes to spec + (b - row0) * 2^n
   long long rows;        // ... and only rows [0, rows) exist there (0: all 2^m)
   unsigned long long* hist;  // histogram modes: [2^(n-1) + 1] counts of |W|/2
-  unsigned long long* hist_over;  // values with |W|/2 >= kHistBins - 1 seen by kHist
+  unsigned long long* hist_over;  // values past the LDS bins seen by the counting pass
 };
 
 // The host passes these structs by value as kernel arguments; both
@@ -355,7 +356,7 @@ __global__ __launch_bounds__(kWG, (min_blocks<N, P_, MODE>())) void k_walsh(cons
         if constexpr (MODE == kHist) atomicAdd(&hl[min(v < 0 ? -v : v, kHistBins - 1)], 1u);
         if constexpr (MODE == kHistBig) {
           const int av = v < 0 ? -v : v;
-          if (av >= kHistBins - 1) atomicAdd(kp.hist + av, 1ull);
+          if (av >= kp.hist_cut) atomicAdd(kp.hist + av, 1ull);
         }
         // a < 2^16 here, so a 32-bit byte offset from a scalar row base suffices
         if constexpr (MODE == kStoreB)
@@ -887,7 +888,13 @@ constexpr int mx_slot_words() { return 16 * CPR + 4; }  // a lane's registers + 
 template <int CPR>
 constexpr int mx_min_waves() { return CPR == 2 ? 2 : 3; }
 
-template <int CPR>
+// HIST: also count every coefficient of the masks b != 0 into the LDS bins
+// min(|W|/2, kMxHistBins - 1) (the last bin only counts the larger values,
+// which the large-value pass then adds one by one); 6 KiB, so two
+// workgroups still share a CU.
+constexpr int kMxHistBins = 1536;
+
+template <int CPR, bool HIST = false>
 __global__ __launch_bounds__(kWG, (mx_min_waves<CPR>())) void k_walsh_mx16(const KParams kp) {
   constexpr int NW = 8;
   constexpr int ROUNDS = 8 / CPR;
@@ -897,6 +904,19 @@ __global__ __launch_bounds__(kWG, (mx_min_waves<CPR>())) void k_walsh_mx16(const
   __shared__ __attribute__((aligned(16))) uint32_t lds[2 * BUF];
   __shared__ int red[64 * 4];  // per mask of a run of 64: the 4 wave maxima
   __shared__ long long s_item;
+  __shared__ uint32_t hl[HIST ? kMxHistBins : 1];
+  if constexpr (HIST)
+    for (int k = threadIdx.x; k < kMxHistBins; k += kWG) hl[k] = 0;  // ordered by the loop's first barrier
+  long long hcount = 0;  // counts since the last flush of hl (workgroup-uniform)
+  auto hist_flush = [&]() {
+    for (int k = threadIdx.x; k < kMxHistBins; k += kWG) {
+      const uint32_t c = hl[k];
+      if (c) {
+        atomicAdd(k == kMxHistBins - 1 ? kp.hist_over : kp.hist + k, (unsigned long long)c);
+        hl[k] = 0;
+      }
+    }
+  };
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -967,6 +987,7 @@ __global__ __launch_bounds__(kWG, (mx_min_waves<CPR>())) void k_walsh_mx16(const
     for (int step = 0; step < C; ++step) {
       const long long k = kfirst + step;
       const bool inrange = k < kend;
+      const bool count = HIST && inrange && k != 0;  // the histogram covers b != 0 (wave-uniform)
       if (step == 0) {
 #pragma unroll
         for (int w = 0; w < NW; ++w) G[w] = 0;
@@ -1059,6 +1080,15 @@ __global__ __launch_bounds__(kWG, (mx_min_waves<CPR>())) void k_walsh_mx16(const
           m1 = fmaxf(fmaxf(m1, fabsf(d0[1])), fabsf(d1[1]));
           m0 = fmaxf(fmaxf(m0, fabsf(d0[2])), fabsf(d1[2]));
           m1 = fmaxf(fmaxf(m1, fabsf(d0[3])), fabsf(d1[3]));
+          if constexpr (HIST) {
+            if (count) {  // |V| = |W|/2 <= 2^15, an exact integer
+#pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                atomicAdd(&hl[min((int)fabsf(d0[i]), kMxHistBins - 1)], 1u);
+                atomicAdd(&hl[min((int)fabsf(d1[i]), kMxHistBins - 1)], 1u);
+              }
+            }
+          }
         }
       }
       const int mx = wave_max((int)fmaxf(m0, m1));
@@ -1082,6 +1112,19 @@ __global__ __launch_bounds__(kWG, (mx_min_waves<CPR>())) void k_walsh_mx16(const
       }
     }
     if (tid == 0 && runmin != 0x7fffffff) atomicMin(jd.nl, runmin);
+    if constexpr (HIST) {
+      // keep every LDS count below 2^32
+      hcount += (long long)C << 16;
+      if (hcount > (1LL << 31)) {
+        __syncthreads();
+        hist_flush();
+        hcount = 0;
+      }
+    }
+  }
+  if constexpr (HIST) {
+    __syncthreads();
+    hist_flush();
   }
 }
 

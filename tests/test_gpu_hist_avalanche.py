@@ -59,6 +59,17 @@ def test_histogram_constant_component_16():
     check_hist(S, 16, 4)
 
 
+def test_histogram_16_values_between_the_bin_limits():
+    """n = 16 components that depend on the low 12 input bits only: W is 16
+    times a 12-bit spectrum, so |W|/2 reaches past 1535 (the last LDS bin of
+    the matrix-core counting pass) and past 2047; both ranges go through the
+    large-value pass."""
+    T = inputs.random_function(12, 6, inputs.rng(20500))
+    S = T[np.arange(1 << 16) & 0xFFF]
+    h = check_hist(S, 16, 6)
+    assert int(h[1535:2047].sum()) > 0 and int(h[2047:].sum()) > 0
+
+
 def test_histogram_aes():
     h = check_hist(inputs.aes_sbox(), 8, 8)
     assert int(np.nonzero(h)[0].max()) == 16  # max |W| = 32, NL = 112
