@@ -366,7 +366,8 @@ sbox_status run_single(const void* S, int n, int m, int eb, int32_t* maxabs, int
     void* args[] = {&jd, &queue, &nq, &lay};
     const void* fn = eb == 1 ? (const void*)&k_prep_single<1> : eb == 2 ? (const void*)&k_prep_single<2>
                                                                         : (const void*)&k_prep_single<4>;
-    s = launch(fn, dim3(1 + (nwords + 255) / 256), dim3(256), args, st);
+    const long long units = (n >= 6 && !sparse) ? (1LL << n) : nwords;  // entries (a wave per 64) or words
+    s = launch(fn, dim3((unsigned)(1 + (units + 255) / 256)), dim3(256), args, st);
     if (s) return s;
   }
 
@@ -1227,7 +1228,8 @@ sbox_status criteria_reg(const void* S, int n, int m, int eb, int32_t* summary, 
     void* args[] = {(void*)&S_, &n_, &m_, &F, &nw_, &summary, &w0, &minwt, &acmax, &pcwt};
     const void* fn = eb == 1 ? (const void*)&k_crit_prep<1> : eb == 2 ? (const void*)&k_crit_prep<2>
                                                                       : (const void*)&k_crit_prep<4>;
-    s = launch(fn, dim3(1 + (nwords + 255) / 256), dim3(256), args, st);
+    const long long units = n >= 6 ? (1LL << n) : nwords;  // entries (a wave per 64) or words
+    s = launch(fn, dim3((unsigned)(1 + (units + 255) / 256)), dim3(256), args, st);
     if (s) return s;
   }
   static const void* const fns[] = {

@@ -1800,6 +1800,31 @@ __device__ void bitslice_words_fp4(const void* S, int m, uint32_t* F, int nwords
   }
 }
 
+// Bit-slicing by a whole wave (dense words, tables of at least 64 entries):
+// lane l reads entry x0 + l (x0 a multiple of 64; one coalesced load), one
+// ballot per output bit gives that bit of all 64 entries, i.e. two words,
+// which are selected into lanes 2 ii, 2 ii + 1 of one register and stored
+// together.  The same words as bitslice_words, from a single table much
+// faster (16 x 16: 8.6 -> 4.4 us); a batch of many small tables stays on
+// the word-per-thread form, where the per-bit selects would cost more than
+// the loads they save.
+template <int EB>
+__device__ void bitslice_wave(const void* S, int m, uint32_t* F, int nwords, long long x0) {
+  const int lane = threadIdx.x & 63;
+  const uint32_t v = load_entry<EB>(S, x0 + lane);
+  const long long w0 = x0 >> 5;
+  for (int i0 = 0; i0 < m; i0 += 32) {
+    const int nb = min(m - i0, 32);
+    uint32_t word = 0;
+    for (int ii = 0; ii < nb; ++ii) {
+      const unsigned long long mask = __ballot((v >> (i0 + ii)) & 1u);
+      word = lane == 2 * ii ? (uint32_t)mask : word;
+      word = lane == 2 * ii + 1 ? (uint32_t)(mask >> 32) : word;
+    }
+    if (lane < 2 * nb) F[(long long)(i0 + (lane >> 1)) * nwords + w0 + (lane & 1)] = word;
+  }
+}
+
 // The words of one job in its layout.
 template <int EB>
 __device__ __forceinline__ void bitslice_job(const JobDesc& jd, int w) {
@@ -2508,6 +2533,11 @@ __global__ __launch_bounds__(256) void k_crit_prep(const void* S, int n, int m, 
     criteria_start(crit, n, w0, minwt, acmax, pcwt);
     return;
   }
+  if (n >= 6) {  // a wave per 64 entries
+    const long long x0 = ((long long)(blockIdx.x - 1) * blockDim.x + (threadIdx.x & ~63));
+    if (x0 < (1LL << n)) bitslice_wave<EB>(S, m, F, nwords, x0);
+    return;
+  }
   const int w = (blockIdx.x - 1) * blockDim.x + threadIdx.x;
   if (w < nwords) bitslice_words<EB>(S, n, m, F, nwords, w);
 }
@@ -2590,11 +2620,17 @@ __global__ __launch_bounds__(256) void k_init_jobs(const JobDesc* jobs, JobDesc 
 }
 
 // A single box in one launch before its transform: workgroup 0 sets the
-// start values, the others bit-slice the table into jd.F (one word a thread).
+// start values, the others bit-slice the table into jd.F (dense words from
+// n = 6 on: a wave per 64 entries; else a word a thread).
 template <int EB>
 __global__ __launch_bounds__(256) void k_prep_single(JobDesc jd, int* queue, int nqueue, int layout) {
   if (blockIdx.x == 0) {
     init_job(jd, true, queue, nqueue, layout);
+    return;
+  }
+  if (jd.n >= 6 && !(jd.flags & kWordsFp4)) {  // dense words: a wave per 64 entries
+    const long long x0 = ((long long)(blockIdx.x - 1) * blockDim.x + (threadIdx.x & ~63));
+    if (x0 < (1LL << jd.n)) bitslice_wave<EB>(jd.S, jd.m, const_cast<uint32_t*>(jd.F), jd.nwords, x0);
     return;
   }
   const int w = (blockIdx.x - 1) * blockDim.x + threadIdx.x;
