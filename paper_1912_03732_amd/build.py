@@ -21,7 +21,10 @@ HIPCC_FLAGS = [
     # keep hipcc from fusing fp32 work into packed-fp32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     # the only floating point here (fp16/fp32 MFMA Hadamard passes) holds finite
-    # integers: no NaN handling and no IEEE-mode canonicalisation around max
+    # integers: no NaN handling and no IEEE-mode canonicalisation around max.
+    # (The kernels read their work-item and group ids through the compiler's
+    # builtins: the device library's functions for them, built in IEEE mode,
+    # cannot be inlined into non-IEEE kernels.)
     "-fno-honor-nans", "-mno-amdgpu-ieee",
     "-Wall", "-Wno-unused-function",
 ]

@@ -47,6 +47,22 @@
 
 namespace sbw {
 
+// Work-item and group indices straight from the compiler's builtins.  The
+// library is built without IEEE mode, and the device library's functions
+// behind threadIdx / blockIdx / blockDim / gridDim (built in IEEE mode) could
+// then not be inlined: every kernel called them, which cost registers and
+// made uniform indices look like per-lane values.
+__device__ __forceinline__ unsigned tid_x() { return __builtin_amdgcn_workitem_id_x(); }
+__device__ __forceinline__ unsigned bid_x() { return __builtin_amdgcn_workgroup_id_x(); }
+__device__ __forceinline__ unsigned bid_y() { return __builtin_amdgcn_workgroup_id_y(); }
+__device__ __forceinline__ unsigned bdim_x() { return __builtin_amdgcn_workgroup_size_x(); }
+__device__ __forceinline__ unsigned gdim_x() { return __builtin_amdgcn_grid_size_x() / __builtin_amdgcn_workgroup_size_x(); }
+
+// Product of two values that fit in 24 bits (v_mul_i32_i24): the operands
+// are sign-extended from bit 23, which the backend turns into the 24-bit
+// multiply, where the device library's __mul24 would be a call here.
+__device__ __forceinline__ int32_t mul24s(int32_t a, int32_t b) { return ((a << 8) >> 8) * ((b << 8) >> 8); }
+
 constexpr int kWG = 256;  // threads per workgroup (4 waves)
 
 // kSlab16: b-major rows of -W/2 as int16 into a slab (the a-major path transposes them)
@@ -198,6 +214,34 @@ __device__ __forceinline__ void load_words(uint32_t (&G)[NW], const uint32_t* p,
   }
 }
 
+// The words of the first mask of a walk, gray(k): the XOR of the slices of
+// its set bits.  Slices are loaded four at a time, the loads of a group in
+// flight together (one after another, each load waited for before the next
+// was issued, this start cost a few microseconds per work item).
+template <int NW>
+__device__ __forceinline__ void gray_start(uint32_t (&G)[NW], const uint32_t* F, long long nwords, long long wb,
+                                           long long gk, int m) {
+#pragma unroll
+  for (int w = 0; w < NW; ++w) G[w] = 0;
+  for (int i0 = 0; i0 < m; i0 += 4) {
+    uint32_t T[4][NW];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int i = i0 + t;
+      if (i < m && ((gk >> i) & 1)) {
+        load_words<NW>(T[t], F + (long long)i * nwords + wb, false);
+      } else {
+#pragma unroll
+        for (int w = 0; w < NW; ++w) T[t][w] = 0;
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int w = 0; w < NW; ++w) G[w] ^= T[t][w];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Maximum (or minimum) over groups of W consecutive lanes, W a power of two:
 // DPP moves inside each row of 16 lanes (quad swaps, half-row and row
@@ -255,7 +299,7 @@ __global__ __launch_bounds__(kWG, (min_blocks<N, P_, MODE>())) void k_walsh(cons
   __shared__ long long s_item;
   __shared__ uint32_t hl[MODE == kHist ? kHistBins : 1];
 
-  const int tid = threadIdx.x;
+  const int tid = tid_x();
   // histogram mode: counts since the last flush of hl (workgroup-uniform)
   long long hcount = 0;
   auto hist_flush = [&]() {
@@ -320,11 +364,7 @@ __global__ __launch_bounds__(kWG, (min_blocks<N, P_, MODE>())) void k_walsh(cons
       if (step == 0) {
 #pragma unroll
         for (int w = 0; w < NW; ++w) G[w] = 0;
-        if (inrange) {
-          const long long gk = gray(k);
-          for (int i = 0; i < jd.m; ++i)
-            if ((gk >> i) & 1) load_words<NW>(G, jd.F + (long long)i * jd.nwords + wb, true);
-        }
+        if (inrange) gray_start<NW>(G, jd.F, jd.nwords, wb, gray(k), jd.m);
       } else if (inrange) {
 #pragma unroll
         for (int w = 0; w < NW; ++w) G[w] ^= Fn[w];
@@ -672,7 +712,7 @@ __global__ __launch_bounds__(kWG, ROUNDS) void k_walsh_mfma16(const KParams kp) 
   __shared__ int red[64 * 4];  // per mask of a run of 64: the 4 wave maxima
   __shared__ long long s_item;
 
-  const int tid = threadIdx.x;
+  const int tid = tid_x();
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int C = kp.chunk;
@@ -727,11 +767,7 @@ __global__ __launch_bounds__(kWG, ROUNDS) void k_walsh_mfma16(const KParams kp) 
       if (step == 0) {
 #pragma unroll
         for (int w = 0; w < NW; ++w) G[w] = 0;
-        if (inrange) {
-          const long long gk = gray(k);
-          for (int i = 0; i < jd.m; ++i)
-            if ((gk >> i) & 1) load_words<NW>(G, jd.F + (long long)i * jd.nwords + wb, true);
-        }
+        if (inrange) gray_start<NW>(G, jd.F, jd.nwords, wb, gray(k), jd.m);
       } else if (inrange) {
 #pragma unroll
         for (int w = 0; w < NW; ++w) G[w] ^= Fn[w];
@@ -906,10 +942,10 @@ __global__ __launch_bounds__(kWG, (mx_min_waves<CPR>())) void k_walsh_mx16(const
   __shared__ long long s_item;
   __shared__ uint32_t hl[HIST ? kMxHistBins : 1];
   if constexpr (HIST)
-    for (int k = threadIdx.x; k < kMxHistBins; k += kWG) hl[k] = 0;  // ordered by the loop's first barrier
+    for (int k = tid_x(); k < kMxHistBins; k += kWG) hl[k] = 0;  // ordered by the loop's first barrier
   long long hcount = 0;  // counts since the last flush of hl (workgroup-uniform)
   auto hist_flush = [&]() {
-    for (int k = threadIdx.x; k < kMxHistBins; k += kWG) {
+    for (int k = tid_x(); k < kMxHistBins; k += kWG) {
       const uint32_t c = hl[k];
       if (c) {
         atomicAdd(k == kMxHistBins - 1 ? kp.hist_over : kp.hist + k, (unsigned long long)c);
@@ -918,7 +954,7 @@ __global__ __launch_bounds__(kWG, (mx_min_waves<CPR>())) void k_walsh_mx16(const
     }
   };
 
-  const int tid = threadIdx.x;
+  const int tid = tid_x();
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int C = kp.chunk;
@@ -991,7 +1027,8 @@ __global__ __launch_bounds__(kWG, (mx_min_waves<CPR>())) void k_walsh_mx16(const
       if (step == 0) {
 #pragma unroll
         for (int w = 0; w < NW; ++w) G[w] = 0;
-        if (inrange) {
+        if (inrange) {  // one load at a time: a work item here walks hundreds of masks, and
+          // the batched start (gray_start) measured 0.8 % slower for this kernel
           const long long gk = gray(k);
           for (int i = 0; i < jd.m; ++i)
             if ((gk >> i) & 1) load_words<NW>(G, jd.F + (long long)i * jd.nwords + wb, true);
@@ -1159,7 +1196,7 @@ __global__ __launch_bounds__(kWG, 4) void k_walsh_mfma12(const KParams kp) {
   __shared__ uint32_t lds[GPW * 32 * 68];     // 8.5 KiB per wave: 32 rows of 68 words
   __shared__ long long s_item;
 
-  const int tid = threadIdx.x;
+  const int tid = tid_x();
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int C = kp.chunk;
@@ -1217,10 +1254,7 @@ __global__ __launch_bounds__(kWG, 4) void k_walsh_mfma12(const KParams kp) {
       const long long k = kfirst + step;
       if (k >= kend) break;  // wave-uniform
       if (step == 0) {
-        G[0] = G[1] = 0;
-        const long long gk = gray(k);
-        for (int i = 0; i < jd.m; ++i)
-          if ((gk >> i) & 1) load_words<NW>(G, jd.F + (long long)i * jd.nwords + wb, true);
+        gray_start<NW>(G, jd.F, jd.nwords, wb, gray(k), jd.m);
       } else {
         G[0] ^= Fn[0];
         G[1] ^= Fn[1];
@@ -1306,7 +1340,7 @@ __global__ __launch_bounds__(kWG, 3) void k_walsh_mx12(const KParams kp) {
   constexpr int GPW = kWG / 64;  // masks (waves) per workgroup
   __shared__ long long s_item;
 
-  const int tid = threadIdx.x;
+  const int tid = tid_x();
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int C = kp.chunk;
@@ -1362,11 +1396,7 @@ __global__ __launch_bounds__(kWG, 3) void k_walsh_mx12(const KParams kp) {
       const long long k = kfirst + step;
       if (k >= kend) break;  // wave-uniform
       if (step == 0) {
-#pragma unroll
-        for (int w = 0; w < NW; ++w) G[w] = 0;
-        const long long gk = gray(k);
-        for (int i = 0; i < jd.m; ++i)
-          if ((gk >> i) & 1) load_words<NW>(G, jd.F + (long long)i * jd.nwords + wb, true);
+        gray_start<NW>(G, jd.F, jd.nwords, wb, gray(k), jd.m);
       } else {
 #pragma unroll
         for (int w = 0; w < NW; ++w) G[w] ^= Fn[w];
@@ -1381,8 +1411,9 @@ __global__ __launch_bounds__(kWG, 3) void k_walsh_mx12(const KParams kp) {
                         (int)(G[3] & 0x44444444u), 0, 0, 0, 0};
       // all 16 first-pass products first, then the casts and second-pass
       // products: each cast waits on a product issued long before, and the
-      // wave keeps the matrix cores busy on its own (132 registers, three
-      // waves a SIMD, measured faster than five waves interleaving the passes)
+      // wave keeps the matrix cores busy on its own (three waves a SIMD:
+      // faster than five waves interleaving the passes, and than two or
+      // four of this form; the host caps the residency at three)
       float m0 = 0.0f, m1 = 0.0f;
       f32x4 d0[8], d1[8];
 #pragma unroll
@@ -1444,7 +1475,7 @@ __global__ __launch_bounds__(kWG, 3) void k_walsh_i8x12(const KParams kp) {
   constexpr uint32_t kFlip = 0xFEFEFEFEu;  // +1 <-> -1 in every byte
   __shared__ long long s_item;
 
-  const int tid = threadIdx.x;
+  const int tid = tid_x();
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int C = kp.chunk;
@@ -1505,11 +1536,7 @@ __global__ __launch_bounds__(kWG, 3) void k_walsh_i8x12(const KParams kp) {
       const long long k = kfirst + step;
       if (k >= kend) break;  // wave-uniform
       if (step == 0) {
-#pragma unroll
-        for (int w = 0; w < NW; ++w) G[w] = 0;
-        const long long gk = gray(k);
-        for (int i = 0; i < jd.m; ++i)
-          if ((gk >> i) & 1) load_words<NW>(G, jd.F + (long long)i * jd.nwords + wb, true);
+        gray_start<NW>(G, jd.F, jd.nwords, wb, gray(k), jd.m);
       } else {
 #pragma unroll
         for (int w = 0; w < NW; ++w) G[w] ^= Fn[w];
@@ -1616,9 +1643,9 @@ __global__ __launch_bounds__(kWG, 2) void k_walsh_big(const BigParams bp) {
   __shared__ int red[kWG / 64];
   __shared__ long long s_item;
 
-  const int tid = threadIdx.x;
+  const int tid = tid_x();
   const int lane = tid & 63;
-  uint32_t* gb = bp.gbuf + (long long)blockIdx.x * NWORDS;
+  uint32_t* gb = bp.gbuf + (long long)bid_x() * NWORDS;
   const long long wbase = (long long)tid * NWT;  // this thread's words
   const long long kend = 1LL << bp.m;
 
@@ -1810,7 +1837,7 @@ __device__ void bitslice_words_fp4(const void* S, int m, uint32_t* F, int nwords
 // the loads they save.
 template <int EB>
 __device__ void bitslice_wave(const void* S, int m, uint32_t* F, int nwords, long long x0) {
-  const int lane = threadIdx.x & 63;
+  const int lane = tid_x() & 63;
   const uint32_t v = load_entry<EB>(S, x0 + lane);
   const long long w0 = x0 >> 5;
   for (int i0 = 0; i0 < m; i0 += 32) {
@@ -1837,7 +1864,7 @@ __device__ __forceinline__ void bitslice_job(const JobDesc& jd, int w) {
 // j = x_lo_low + 2^B * x_hi, bit i of S[x_hi * 2^16 + x_lo].
 template <int EB>
 __global__ __launch_bounds__(256) void k_bitslice_big(const void* S, int L, int m, uint32_t* FT, int nwords) {
-  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  const int w = bid_x() * bdim_x() + tid_x();
   if (w >= nwords) return;
   const int B = 5 - L;
   uint32_t v[32];
@@ -1855,10 +1882,10 @@ __global__ __launch_bounds__(256) void k_bitslice_big(const void* S, int L, int 
   }
 }
 
-// Batched: blockIdx.y selects the job, threads stride over its words.
+// Batched: bid_y() selects the job, threads stride over its words.
 __global__ __launch_bounds__(64) void k_bitslice_jobs(const JobDesc* jobs) {
-  const JobDesc jd = jobs[blockIdx.y];
-  for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < jd.nwords; w += gridDim.x * blockDim.x) {
+  const JobDesc jd = jobs[bid_y()];
+  for (int w = bid_x() * bdim_x() + tid_x(); w < jd.nwords; w += gdim_x() * bdim_x()) {
     if (jd.s_elem_bytes == 1) bitslice_job<1>(jd, w);
     else if (jd.s_elem_bytes == 2) bitslice_job<2>(jd, w);
     else bitslice_job<4>(jd, w);
@@ -1889,7 +1916,7 @@ struct CritParams {
 __device__ __forceinline__ void lds_fwht(int32_t* buf, int n) {
   const int half = 1 << (n - 1);
   for (int h = 1; h <= half; h <<= 1) {
-    for (int p = threadIdx.x; p < half; p += blockDim.x) {
+    for (int p = tid_x(); p < half; p += bdim_x()) {
       const int i = ((p & ~(h - 1)) << 1) | (p & (h - 1));
       const int32_t u = buf[i], v = buf[i + h];
       buf[i] = (int32_t)((uint32_t)u + (uint32_t)v);
@@ -1902,10 +1929,10 @@ __device__ __forceinline__ void lds_fwht(int32_t* buf, int n) {
 __device__ __forceinline__ int block_sum(int v, int* red) {
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  if ((tid_x() & 63) == 0) red[tid_x() >> 6] = v;
   __syncthreads();
   int r = red[0];
-  for (int i = 1; i < (int)(blockDim.x >> 6); ++i) r += red[i];
+  for (int i = 1; i < (int)(bdim_x() >> 6); ++i) r += red[i];
   __syncthreads();
   return r;
 }
@@ -1913,10 +1940,10 @@ __device__ __forceinline__ int block_sum(int v, int* red) {
 template <bool IS_MAX>
 __device__ __forceinline__ int block_reduce(int v, int* red) {
   v = group_reduce<64, IS_MAX>(v);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  if ((tid_x() & 63) == 0) red[tid_x() >> 6] = v;
   __syncthreads();
   int r = red[0];
-  for (int i = 1; i < (int)(blockDim.x >> 6); ++i) r = IS_MAX ? max(r, red[i]) : min(r, red[i]);
+  for (int i = 1; i < (int)(bdim_x() >> 6); ++i) r = IS_MAX ? max(r, red[i]) : min(r, red[i]);
   __syncthreads();
   return r;
 }
@@ -1930,13 +1957,13 @@ __global__ __launch_bounds__(256) void k_criteria(const CritParams p) {
   const long long M = 1LL << p.m;
   // this workgroup's share of the aggregates (thread 0), added once at the end
   int g_nl = N >> 1, g_unb = 0, g_mw = n + 1, g_ac = 0, g_pw = n + 1;
-  for (long long b = blockIdx.x + 1; b < M; b += gridDim.x) {
-    for (int x = threadIdx.x; x < N; x += blockDim.x)
+  for (long long b = bid_x() + 1; b < M; b += gdim_x()) {
+    for (int x = tid_x(); x < N; x += bdim_x())
       buf[x] = (__builtin_popcount((uint32_t)b & load_entry<EB>(p.S, x)) & 1) ? -1 : 1;
     __syncthreads();
     lds_fwht(buf, n);
     int mx = 0, mw = n + 1, w0 = 0;
-    for (int a = threadIdx.x; a < N; a += blockDim.x) {
+    for (int a = tid_x(); a < N; a += bdim_x()) {
       const int v = buf[a];
       mx = max(mx, v < 0 ? -v : v);
       if (a == 0) w0 = v;
@@ -1949,7 +1976,7 @@ __global__ __launch_bounds__(256) void k_criteria(const CritParams p) {
     mw = block_reduce<false>(mw, red);
     lds_fwht(buf, n);
     int ac = 0, pw = n + 1;
-    for (int d = threadIdx.x; d < N; d += blockDim.x) {
+    for (int d = tid_x(); d < N; d += bdim_x()) {
       if (d == 0) continue;
       const int r = (int)((uint32_t)buf[d] << 2) >> n;  // 4 V(d) / 2^n, exact
       ac = max(ac, r < 0 ? -r : r);
@@ -1957,7 +1984,7 @@ __global__ __launch_bounds__(256) void k_criteria(const CritParams p) {
     }
     ac = block_reduce<true>(ac, red);
     pw = block_reduce<false>(pw, red);
-    if (threadIdx.x == 0) {
+    if (tid_x() == 0) {
       if (p.w0) p.w0[b] = w0;
       if (p.minwt) p.minwt[b] = mw;
       if (p.acmax) p.acmax[b] = ac;
@@ -1970,7 +1997,7 @@ __global__ __launch_bounds__(256) void k_criteria(const CritParams p) {
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
+  if (tid_x() == 0) {
     atomicMin(&p.crit[0], g_nl);
     if (g_unb) atomicAdd(&p.crit[1], g_unb);
     atomicMin(&p.crit[2], g_mw);
@@ -2007,7 +2034,7 @@ struct CritRegParams {
   const uint32_t* F;  // [m][2^(n-5)] bit-sliced words
   int m;
   long long chunk;    // Gray indices per group
-  int32_t* part;      // [gridDim.x][8] per-workgroup aggregates (nl, unbalanced, minwt, acmax, pcwt)
+  int32_t* part;      // [gdim_x()][8] per-workgroup aggregates (nl, unbalanced, minwt, acmax, pcwt)
   int32_t* w0;
   int32_t* minwt;
   int32_t* acmax;
@@ -2116,14 +2143,14 @@ __global__ __launch_bounds__(crit_reg_wg(N)) void k_crit_reg(const CritRegParams
   __shared__ __attribute__((aligned(16))) int32_t lds[GPB * C::GWORDS];
   __shared__ int xr[GPB][GL > 64 ? GL / 64 : 1];
   __shared__ int agg[GPB][5];
-  const int tid = threadIdx.x;
+  const int tid = tid_x();
   const int grp = tid / GL;
   const int l = tid % GL;
   int32_t* buf = lds + grp * C::GWORDS;
   auto at = [](int e) { return (e >> RB) * ROW + (e & (R - 1)); };  // LDS word of entry e
   const int nwords = 1 << (N - 5);
   const long long kend = 1LL << p.m;
-  const long long kfirst = 1 + ((long long)blockIdx.x * GPB + grp) * p.chunk;
+  const long long kfirst = 1 + ((long long)bid_x() * GPB + grp) * p.chunk;
   const int lw = __builtin_popcount(l);
 
   // this group's share of the aggregates, folded per workgroup at the end
@@ -2176,7 +2203,7 @@ __global__ __launch_bounds__(crit_reg_wg(N)) void k_crit_reg(const CritRegParams
     int mxsq = 0;
 #pragma unroll
     for (int j = 0; j < R; ++j) {
-      const int32_t s = __mul24(v[j], v[j]);
+      const int32_t s = mul24s(v[j], v[j]);
       mxsq = max(mxsq, s);
       ci[__builtin_popcount(j)] |= (uint32_t)s;
       v[j] = s;
@@ -2245,7 +2272,7 @@ __global__ __launch_bounds__(crit_reg_wg(N)) void k_crit_reg(const CritRegParams
       g_ac = max(g_ac, agg[q][3]);
       g_pw = min(g_pw, agg[q][4]);
     }
-    int32_t* o = p.part + 8 * blockIdx.x;
+    int32_t* o = p.part + 8 * bid_x();
     o[0] = g_nl;
     o[1] = g_unb;
     o[2] = g_mw;
@@ -2295,7 +2322,7 @@ __global__ __launch_bounds__(1 << (N - 6), 4) void k_crit_wide(const CritRegPara
   // the lane's two bit-sliced words of the current mask (the Gray-code walk
   // state), kept here rather than in registers: 1 KiB per wave
   __shared__ uint2 gw[64 * NWAV];
-  const int l = threadIdx.x;
+  const int l = tid_x();
   const int w = __builtin_amdgcn_readfirstlane(l >> 6), i = l & 63;  // wave index: uniform, scalar branches
   const bool first_turn = w < NB;
   int32_t* blk = lds + (w % NB) * 64 * ROW;  // this wave's block for A <-> M
@@ -2303,10 +2330,18 @@ __global__ __launch_bounds__(1 << (N - 6), 4) void k_crit_wide(const CritRegPara
   // 32-bit mask counters (m <= 24): their compares stay on the scalar unit
   const int kend = 1 << p.m;
   const int chunk = (int)p.chunk;
-  const int kfirst = 1 + (int)blockIdx.x * chunk;
-  // running aggregates: every value that enters them is uniform, so they
-  // stay in scalar registers (wave 0's copy is the workgroup's)
-  int g_nl = 1 << (N - 1), g_unb = 0, g_mw = N + 1, g_ac = 0, g_pw = N + 1;
+  const int kfirst = 1 + (int)bid_x() * chunk;
+  // running aggregates (nl, unbalanced, min weight, abs indicator, min PC
+  // weight) in LDS, updated by thread 0 only: nothing loop-carried for them
+  // in registers
+  __shared__ int agg[5];
+  if (tid_x() == 0) {
+    agg[0] = 1 << (N - 1);
+    agg[1] = 0;
+    agg[2] = N + 1;
+    agg[3] = 0;
+    agg[4] = N + 1;
+  }
   auto words = [&](int b, int lane) {  // bit slice b, the lane's two words
     return reinterpret_cast<const uint2*>(p.F + b * nwords)[lane];
   };
@@ -2404,7 +2439,7 @@ __global__ __launch_bounds__(1 << (N - 6), 4) void k_crit_wide(const CritRegPara
     int mxsq = 0;
 #pragma unroll
     for (int j = 0; j < R; ++j) {
-      const int32_t s = __mul24(v[j], v[j]);
+      const int32_t s = mul24s(v[j], v[j]);
       mxsq = max(mxsq, s);
       ci[__builtin_popcount(j)] |= (uint32_t)s;
       v[j] = s;
@@ -2446,29 +2481,24 @@ __global__ __launch_bounds__(1 << (N - 6), 4) void k_crit_wide(const CritRegPara
     pw = __builtin_amdgcn_readfirstlane(crit_group_reduce<64 * NWAV, false>(pw, xr, l));
     if (mw > N) mw = N + 1;
     if (pw > N) pw = N + 1;
-    if (valid) {
+    if (valid && l == 0) {
       const int umax = (int)rintf(sqrtf((float)mxsq));  // mxsq is a perfect square <= 2^30
-      if (l == 0) {
-        const int b = (int)gray(k);
-        if (p.w0) p.w0[b] = w0;
-        if (p.minwt) p.minwt[b] = mw;
-        if (p.acmax) p.acmax[b] = ac;
-        if (p.pcwt) p.pcwt[b] = pw;
-      }
-      g_nl = min(g_nl, (1 << (N - 1)) - __builtin_amdgcn_readfirstlane(umax));
-      g_unb += w0 != 0;
-      g_mw = min(g_mw, mw);
-      g_ac = max(g_ac, ac);
-      g_pw = min(g_pw, pw);
+      const int b = (int)gray(k);
+      if (p.w0) p.w0[b] = w0;
+      if (p.minwt) p.minwt[b] = mw;
+      if (p.acmax) p.acmax[b] = ac;
+      if (p.pcwt) p.pcwt[b] = pw;
+      agg[0] = min(agg[0], (1 << (N - 1)) - umax);
+      agg[1] += w0 != 0;
+      agg[2] = min(agg[2], mw);
+      agg[3] = max(agg[3], ac);
+      agg[4] = min(agg[4], pw);
     }
   }
   if (l == 0) {
-    int32_t* o = p.part + 8 * blockIdx.x;
-    o[0] = g_nl;
-    o[1] = g_unb;
-    o[2] = g_mw;
-    o[3] = g_ac;
-    o[4] = g_pw;
+    int32_t* o = p.part + 8 * bid_x();
+#pragma unroll
+    for (int q = 0; q < 5; ++q) o[q] = agg[q];
   }
 }
 
@@ -2478,7 +2508,7 @@ __global__ __launch_bounds__(1 << (N - 6), 4) void k_crit_wide(const CritRegPara
 __global__ __launch_bounds__(256) void k_crit_reg_finish(const int32_t* part, int nwg, int32_t* crit) {
   __shared__ int red[4];
   int nl = 0x7fffffff, unb = 0, mw = 0x7fffffff, ac = 0, pw = 0x7fffffff;
-  for (int i = threadIdx.x; i < nwg; i += blockDim.x) {
+  for (int i = tid_x(); i < nwg; i += bdim_x()) {
     const int32_t* o = part + 8 * i;
     nl = min(nl, o[0]);
     unb += o[1];
@@ -2491,7 +2521,7 @@ __global__ __launch_bounds__(256) void k_crit_reg_finish(const int32_t* part, in
   ac = block_reduce<true>(ac, red);
   pw = block_reduce<false>(pw, red);
   unb = block_sum(unb, red);
-  if (threadIdx.x == 0) {
+  if (tid_x() == 0) {
     crit[0] = min(crit[0], nl);
     crit[1] += unb;
     crit[2] = min(crit[2], mw) - 1;
@@ -2504,7 +2534,7 @@ __global__ __launch_bounds__(256) void k_crit_reg_finish(const int32_t* part, in
 // crit[] start values; per-mask outputs at b = 0 are defined as 0.
 __device__ __forceinline__ void criteria_start(int32_t* crit, int n, int32_t* w0, int32_t* minwt, int32_t* acmax,
                                                int32_t* pcwt) {
-  if (threadIdx.x == 0) {
+  if (tid_x() == 0) {
     crit[0] = 1 << (n - 1);
     crit[1] = 0;
     crit[2] = n + 1;
@@ -2529,22 +2559,22 @@ __global__ void k_criteria_init(int32_t* crit, int n, int32_t* w0, int32_t* minw
 template <int EB>
 __global__ __launch_bounds__(256) void k_crit_prep(const void* S, int n, int m, uint32_t* F, int nwords, int32_t* crit,
                                                    int32_t* w0, int32_t* minwt, int32_t* acmax, int32_t* pcwt) {
-  if (blockIdx.x == 0) {
+  if (bid_x() == 0) {
     criteria_start(crit, n, w0, minwt, acmax, pcwt);
     return;
   }
   if (n >= 6) {  // a wave per 64 entries
-    const long long x0 = ((long long)(blockIdx.x - 1) * blockDim.x + (threadIdx.x & ~63));
+    const long long x0 = ((long long)(bid_x() - 1) * bdim_x() + (tid_x() & ~63));
     if (x0 < (1LL << n)) bitslice_wave<EB>(S, m, F, nwords, x0);
     return;
   }
-  const int w = (blockIdx.x - 1) * blockDim.x + threadIdx.x;
+  const int w = (bid_x() - 1) * bdim_x() + tid_x();
   if (w < nwords) bitslice_words<EB>(S, n, m, F, nwords, w);
 }
 
 // Orders from the minimum weights: CI = minwt - 1, resiliency = CI if balanced.
 __global__ void k_criteria_finish(int32_t* crit) {
-  if (threadIdx.x == 0) {
+  if (tid_x() == 0) {
     crit[2] = crit[2] - 1;
     crit[3] = crit[1] == 0 ? crit[2] : -1;
     crit[5] = crit[5] - 1;
@@ -2563,9 +2593,9 @@ __global__ __launch_bounds__(256) void k_transpose_slab16(const int16_t* slab, i
                                                           long long b0, int B, int wscale, const void* S, int eb) {
   __shared__ int32_t tile[64][65];  // tile[j][p]: entries a0 + 2p, a0 + 2p + 1 of row j
   const long long N = 1LL << n;
-  const long long a0 = (long long)blockIdx.x * 128;
-  const int j0 = blockIdx.y * 64;
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const long long a0 = (long long)bid_x() * 128;
+  const int j0 = bid_y() * 64;
+  const int tx = tid_x() & 63, ty = tid_x() >> 6;
   for (int r = ty; r < 64; r += 4) {
     const int j = j0 + r;
     if (j < B && a0 + 2 * tx < N) tile[r][tx] = reinterpret_cast<const int32_t*>(slab + (long long)j * N + a0)[tx];
@@ -2596,15 +2626,15 @@ __global__ __launch_bounds__(256) void k_transpose_slab16(const int16_t* slab, i
 // queue counters).
 __device__ __forceinline__ void init_job(const JobDesc& jd, bool first, int* queue, int nqueue, int layout) {
   if (first) {
-    for (int i = threadIdx.x; i < nqueue; i += blockDim.x) queue[i] = 0;
+    for (int i = tid_x(); i < nqueue; i += bdim_x()) queue[i] = 0;
   }
-  if (threadIdx.x == 0) {
+  if (tid_x() == 0) {
     *jd.nl = 1 << (jd.n - 1);
     if (jd.maxabs) jd.maxabs[0] = 1 << jd.n;
   }
   if (jd.spec) {
     const long long N = 1LL << jd.n;
-    for (long long a = threadIdx.x; a < N; a += blockDim.x) {
+    for (long long a = tid_x(); a < N; a += bdim_x()) {
       const int v = (a == 0) ? (int)(N >> 1) * -jd.wscale : 0;  // 2^n (W) or 2^(n-1) (LAT)
       if (layout == 1) jd.spec[a] = v;
       else jd.spec[a << jd.m] = v;
@@ -2614,7 +2644,7 @@ __device__ __forceinline__ void init_job(const JobDesc& jd, bool first, int* que
 
 __global__ __launch_bounds__(256) void k_init_jobs(const JobDesc* jobs, JobDesc job0, int njobs,
                                                    int* queue, int nqueue, int layout) {
-  const int j = blockIdx.x;
+  const int j = bid_x();
   if (j >= njobs) return;
   init_job(jobs ? jobs[j] : job0, j == 0, queue, nqueue, layout);
 }
@@ -2624,23 +2654,23 @@ __global__ __launch_bounds__(256) void k_init_jobs(const JobDesc* jobs, JobDesc 
 // n = 6 on: a wave per 64 entries; else a word a thread).
 template <int EB>
 __global__ __launch_bounds__(256) void k_prep_single(JobDesc jd, int* queue, int nqueue, int layout) {
-  if (blockIdx.x == 0) {
+  if (bid_x() == 0) {
     init_job(jd, true, queue, nqueue, layout);
     return;
   }
   if (jd.n >= 6 && !(jd.flags & kWordsFp4)) {  // dense words: a wave per 64 entries
-    const long long x0 = ((long long)(blockIdx.x - 1) * blockDim.x + (threadIdx.x & ~63));
+    const long long x0 = ((long long)(bid_x() - 1) * bdim_x() + (tid_x() & ~63));
     if (x0 < (1LL << jd.n)) bitslice_wave<EB>(jd.S, jd.m, const_cast<uint32_t*>(jd.F), jd.nwords, x0);
     return;
   }
-  const int w = (blockIdx.x - 1) * blockDim.x + threadIdx.x;
+  const int w = (bid_x() - 1) * bdim_x() + tid_x();
   if (w < jd.nwords) bitslice_job<EB>(jd, w);
 }
 
 // Zero `count` ints (queue counters, per-batch maxima) without a memset node.
 __global__ __launch_bounds__(256) void k_zero(int* p, long long count) {
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < count;
-       i += (long long)gridDim.x * blockDim.x)
+  for (long long i = bid_x() * (long long)bdim_x() + tid_x(); i < count;
+       i += (long long)gdim_x() * bdim_x())
     p[i] = 0;
 }
 
@@ -2655,7 +2685,7 @@ __global__ __launch_bounds__(256) void k_combine(int32_t* T, long long kcount, i
                                                  long long kbase, long long mend) {
   const int L = nblk_log;
   const long long per_slot = (1LL << 16) << (L - R);  // threads per slot
-  const long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  const long long idx = bid_x() * (long long)bdim_x() + tid_x();
   const long long slot = idx / per_slot;
   int mx = 0;
   if (slot < kcount) {
@@ -2698,14 +2728,14 @@ __global__ __launch_bounds__(256) void k_combine(int32_t* T, long long kcount, i
   if constexpr (LAST) {
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) mx = max(mx, __shfl_xor(mx, o, 64));
-    if ((threadIdx.x & 63) == 0 && slot < kcount) atomicMax(&slotmax[slot], mx);
+    if ((tid_x() & 63) == 0 && slot < kcount) atomicMax(&slotmax[slot], mx);
   }
 }
 
 // n > 16: per-mask maxima of the batch -> maxabs and NL.
 __global__ __launch_bounds__(256) void k_finalize_batch(const int* slotmax, long long kcount, long long kbase,
                                                         long long mend, int n, int32_t* maxabs, int32_t* nl) {
-  const long long s = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  const long long s = bid_x() * (long long)bdim_x() + tid_x();
   int cand = 0x7fffffff;
   if (s < kcount) {
     const long long k = kbase + s;
@@ -2717,7 +2747,7 @@ __global__ __launch_bounds__(256) void k_finalize_batch(const int* slotmax, long
   }
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) cand = min(cand, __shfl_xor(cand, o, 64));
-  if ((threadIdx.x & 63) == 0 && cand != 0x7fffffff) atomicMin(nl, cand);
+  if ((tid_x() & 63) == 0 && cand != 0x7fffffff) atomicMin(nl, cand);
 }
 
 // ---------------------------------------------------------------------------
@@ -2734,8 +2764,8 @@ __global__ __launch_bounds__(256) void k_deriv_count(const void* S, int n, int m
   const long long half = 1LL << (n - 1);
   const long long total = (long long)n * half;
   const uint32_t mmask = (m >= 32) ? 0xffffffffu : ((1u << m) - 1u);
-  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total;
-       t += (long long)gridDim.x * blockDim.x) {
+  for (long long t = bid_x() * (long long)bdim_x() + tid_x(); t < total;
+       t += (long long)gdim_x() * bdim_x()) {
     const int i = (int)(t >> (n - 1));
     const long long j = t & (half - 1);
     const long long x = ((j >> i) << (i + 1)) | (j & ((1LL << i) - 1));
@@ -2751,9 +2781,9 @@ __global__ __launch_bounds__(256) void k_deriv_count(const void* S, int n, int m
 // int32 holds it.
 __global__ __launch_bounds__(256) void k_fwht_pass(int32_t* data, int mlog, int lo, int R, int cwlog) {
   __shared__ int32_t t[4096];
-  const int tid = threadIdx.x;
+  const int tid = tid_x();
   const int CW = 1 << cwlog, TILE = 1 << (R + cwlog);
-  long long blk = blockIdx.x;
+  long long blk = bid_x();
   const long long ncolb = 1LL << (lo - cwlog);
   const long long colb = blk % ncolb;
   blk /= ncolb;
@@ -2784,7 +2814,7 @@ __global__ __launch_bounds__(256) void k_fwht_pass(int32_t* data, int mlog, int 
 __global__ __launch_bounds__(256) void k_avalanche_summary(const int32_t* r, int n, int m, const int32_t* maxabs,
                                                            int32_t* summary) {
   __shared__ int s_val[3];
-  const int tid = threadIdx.x;
+  const int tid = tid_x();
   if (tid == 0) {
     s_val[0] = 0;
     s_val[1] = m >= 2 ? 0 : -1;
