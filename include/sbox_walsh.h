@@ -140,6 +140,12 @@ sbox_status sbox_scratch_release(void* stream);
  *                 more masks be processed per pass.
  *   tuning        NULL for defaults.
  * Performs no allocation and no host synchronisation; graph-capturable.
+ * An a-major spectrum (or LAT) with n = m >= 14 checks on the device
+ * whether S is a permutation; if it is, it writes the b-major matrix of
+ * S^-1, which is the a-major matrix of S (W_{S^-1}(u, v) = W_S(v, u),
+ * Eq. 1 with y = S(x)), instead of transposing slabs: about half the time
+ * at n = m = 16.  The decision is taken again on every call (and on every
+ * replay of a captured call) from the table's contents at that time.
  */
 sbox_status sbox_walsh_nl_ex(const void* S, int n, int m, int s_elem_bytes,
                              int32_t* maxabs_per_b, int32_t* nl,

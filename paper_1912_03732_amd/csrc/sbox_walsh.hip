@@ -259,6 +259,12 @@ bool use_slab(int n, int m, int layout) { return layout == 2 && n <= 16 && n >= 
 #endif
 long long slab_rows(int n, int m) { return std::min(1LL << m, std::max(64LL, (1LL << SBW_SLAB_LOG) >> n)); }
 size_t slab_bytes(int n, int m) { return align256(((size_t)slab_rows(n, m) << n) * 2); }  // int16 rows
+// The route for a permutation beside the slabs where there are two or more
+// of them (n = m >= 14; at n = m = 12 the one slab costs about what the
+// route's extra launches do), and its workspace: the decision flag and a
+// spare NL word, the uint16 inverse table and its bit-sliced words.
+bool use_perm_route(int n, int m, int layout) { return use_slab(n, m, layout) && n == m && n >= 14; }
+size_t perm_route_bytes(int n) { return 256 + align256(size_t(2) << n) + align256(size_t(n) << (n - 3)); }
 
 // Chunk and grid for a kernel with `groups` thread groups per workgroup over
 // `masks` masks per job x `njobs` jobs.
@@ -325,6 +331,44 @@ sbox_status run_big(const void* S, int n, int m, int eb, int32_t* maxabs, int32_
   return launch(fn, dim3((unsigned)grid), dim3(kWG), args, st);
 }
 
+// One transform launch over all 2^m masks of a single box (n <= 16): the
+// matrix-core kernel for the plain maximum where it is the default (or the
+// tuning asks for it), else k_walsh in `mode`.  `kp` carries the caller's
+// fields (histogram, gate) in and the launched configuration out.
+sbox_status launch_transform(const JobDesc& jd, int mode, const sbox_tuning* tun, int cus, int* queue,
+                             hipStream_t st, KParams* kp) {
+  const int n = jd.n;
+  const void* fn = nullptr;
+  int groups = 1;
+  if (mode == kMax && use_mfma(n, tun)) {
+    fn = (const void*)mfma_kernel(n, tun);
+    groups = mfma_groups(n);
+  } else {
+    const int p = (tun && tun->split_p) ? tun->split_p : default_split(n);
+    if (n > 8 && !split_valid(n, p)) return fail(SBOX_ERR_INVALID_ARG, "split_p=%d invalid for n=%d", p, n);
+    fn = (const void*)lookup_kernel(n, n <= 8 ? n : p, mode);
+    if (!fn) return fail(SBOX_ERR_INVALID_ARG, "no kernel for n=%d split_p=%d mode=%d", n, p, mode);
+    groups = kWG >> (n <= 8 ? 0 : n - p);
+  }
+  int occ = 1;
+  sbox_status s = occupancy(fn, &occ);
+  if (s) return s;
+  const long long M = 1LL << jd.m;
+  const int grid_cap = (tun && tun->grid) ? tun->grid : occ * cus;
+  int chunk = 1;
+  pick_chunk(M, groups, grid_cap, tun ? tun->chunk : 0, &chunk);
+  const long long per_item = (long long)groups * chunk;
+  kp->jobs = nullptr;
+  kp->job0 = jd;
+  kp->njobs = 1;
+  kp->chunk = chunk;
+  kp->queue = queue;
+  kp->total_items = (M + per_item - 1) / per_item;
+  const int grid = (int)std::min<long long>(grid_cap, kp->total_items);
+  void* args[] = {kp};
+  return launch(fn, dim3(grid), dim3(kWG), args, st);
+}
+
 // ------------------------------------------------------- one S-box call ----
 sbox_status run_single(const void* S, int n, int m, int eb, int32_t* maxabs, int32_t* nl, int32_t* spec,
                        int layout_arg, void* ws, size_t ws_bytes, const sbox_tuning* tun, hipStream_t st,
@@ -380,6 +424,65 @@ sbox_status run_single(const void* S, int n, int m, int eb, int32_t* maxabs, int
   }
 
   if (n <= 16 && use_slab(n, m, layout)) {
+    // A box with n = m may be a permutation: then its a-major matrix is the
+    // b-major matrix of the inverse map, written without slabs.  The device
+    // decides (*bij); the launches of the route not taken return at once.
+    const int* bij = nullptr;
+    int qi = 1;
+    if (use_perm_route(n, m, layout)) {
+      char* extra = reinterpret_cast<char*>(ws) + kQueueBytes + f_bytes(n, m) + slab_bytes(n, m);
+      int* flag = reinterpret_cast<int*>(extra);
+      int32_t* spare_nl = flag + 1;
+      uint16_t* inv = reinterpret_cast<uint16_t*>(extra + 256);
+      uint32_t* Finv = reinterpret_cast<uint32_t*>(extra + 256 + align256(size_t(2) << n));
+      const void* S_ = S;
+      int n_ = n;
+      {
+        void* args[] = {(void*)&S_, &n_, &inv, &flag};
+        const void* fn = eb == 1 ? (const void*)&k_perm_scatter<1> : eb == 2 ? (const void*)&k_perm_scatter<2>
+                                                                             : (const void*)&k_perm_scatter<4>;
+        s = launch(fn, dim3((unsigned)(((1LL << n) + 255) / 256)), dim3(256), args, st);
+        if (s) return s;
+      }
+      JobDesc ji{};
+      ji.S = inv;
+      ji.F = Finv;
+      ji.maxabs = nullptr;
+      ji.nl = maxabs ? spare_nl : nl;  // NL(S^-1) = NL(S) for a permutation
+      ji.spec = spec;
+      ji.n = n;
+      ji.m = m;
+      ji.nwords = 1 << (n - 5);
+      ji.s_elem_bytes = 2;
+      ji.wscale = wscale;
+      {
+        int* noq = nullptr;
+        int nq = 0;
+        void* args[] = {(void*)&S_, &ji, &flag, &noq, &nq};
+        const void* fn = eb == 1 ? (const void*)&k_perm_check_prep<1> : eb == 2 ? (const void*)&k_perm_check_prep<2>
+                                                                                 : (const void*)&k_perm_check_prep<4>;
+        s = launch(fn, dim3((unsigned)(1 + ((1LL << n) + 255) / 256)), dim3(256), args, st);
+        if (s) return s;
+      }
+      // for a permutation: the maxima of S per mask b (if asked for) from the
+      // fused kernel, and the rows of S^-1 with the NL
+      if (maxabs) {
+        KParams kp{};
+        kp.gate = flag;
+        kp.gate_run = 1;
+        s = launch_transform(jd, kMax, tun, cus, queue + 1, st, &kp);
+        if (s) return s;
+      }
+      sbox_tuning tb = tun ? *tun : sbox_tuning{};
+      tb.split_p = 0;  // the store modes exist for the default split only
+      KParams kp{};
+      kp.gate = flag;
+      kp.gate_run = 1;
+      s = launch_transform(ji, kStoreB, &tb, cus, queue + 2, st, &kp);
+      if (s) return s;
+      bij = flag;
+      qi = 3;
+    }
     // b-major rows of each aligned block of masks into the slab, then transpose
     const int p = default_split(n);
     KFn fn = lookup_kernel(n, p, kSlab16);
@@ -396,7 +499,6 @@ sbox_status run_single(const void* S, int n, int m, int eb, int32_t* maxabs, int
     pick_chunk(rows, groups, grid_cap, tun ? tun->chunk : 0, &chunk);
     const long long per_item = (long long)groups * chunk;
     const long long M = 1LL << m;
-    int qi = 1;
     for (long long b0 = 0; b0 < M; b0 += rows, ++qi) {
       if (qi >= 64) {
         int* q = queue + 1;
@@ -419,6 +521,8 @@ sbox_status run_single(const void* S, int n, int m, int eb, int32_t* maxabs, int
       kp.row0 = b0;
       kp.rows = rows;
       kp.total_items = (rows + per_item - 1) / per_item;
+      kp.gate = bij;
+      kp.gate_run = 0;
       const int grid = (int)std::min<long long>(grid_cap, kp.total_items);
       void* args[] = {&kp};
       s = launch((const void*)fn, dim3(grid), dim3(kWG), args, st);
@@ -427,7 +531,7 @@ sbox_status run_single(const void* S, int n, int m, int eb, int32_t* maxabs, int
       long long b0_ = b0;
       const int16_t* slab_ = reinterpret_cast<const int16_t*>(slab);
       const void* S_ = jd.S;
-      void* targs[] = {(void*)&slab_, &n_, &spec, &m_, &b0_, &B_, &wsc, (void*)&S_, &eb_};
+      void* targs[] = {(void*)&slab_, &n_, &spec, &m_, &b0_, &B_, &wsc, (void*)&S_, &eb_, (void*)&bij};
       s = launch((const void*)&k_transpose_slab16,
                  dim3((unsigned)(((1LL << n) + 127) / 128), (unsigned)((rows + 63) / 64)), dim3(256), targs, st);
       if (s) return s;
@@ -473,58 +577,14 @@ sbox_status run_single(const void* S, int n, int m, int eb, int32_t* maxabs, int
     return launch((const void*)fnb, dim3(gridb), dim3(kWG), argsb, st);
   }
 
-  if (layout == 0 && !hist && use_mfma(n, tun)) {
-    const void* fn = (const void*)mfma_kernel(n, tun);
-    int occ = 1;
-    s = occupancy(fn, &occ);
-    if (s) return s;
-    const long long M = 1LL << m;
-    const int grid_cap = (tun && tun->grid) ? tun->grid : occ * cus;
-    const int groups = mfma_groups(n);
-    int chunk = 1;
-    pick_chunk(M, groups, grid_cap, tun ? tun->chunk : 0, &chunk);
-    const long long per_item = (long long)groups * chunk;
-    KParams kp{};
-    kp.job0 = jd;
-    kp.njobs = 1;
-    kp.chunk = chunk;
-    kp.queue = queue;
-    kp.total_items = (M + per_item - 1) / per_item;
-    const int grid = (int)std::min<long long>(grid_cap, kp.total_items);
-    void* args[] = {&kp};
-    return launch(fn, dim3(grid), dim3(kWG), args, st);
-  }
-
   if (n <= 16) {
-    const int p = (tun && tun->split_p) ? tun->split_p : default_split(n);
-    const int mode = hist ? (int)kHist : mode_of(layout);
-    if (n > 8 && !split_valid(n, p)) return fail(SBOX_ERR_INVALID_ARG, "split_p=%d invalid for n=%d", p, n);
-    KFn fn = lookup_kernel(n, n <= 8 ? n : p, mode);
-    if (!fn) return fail(SBOX_ERR_INVALID_ARG, "no kernel for n=%d split_p=%d layout=%d", n, p, layout);
-    int occ = 1;
-    s = occupancy((const void*)fn, &occ);
-    if (s) return s;
-    const int Q = n <= 8 ? 0 : n - p;
-    const int groups = kWG >> Q;
-    const long long M = 1LL << m;
-    int grid_cap = (tun && tun->grid) ? tun->grid : occ * cus;
-    int chunk = 1;
-    pick_chunk(M, groups, grid_cap, tun ? tun->chunk : 0, &chunk);
-    const long long per_item = (long long)groups * chunk;
     KParams kp{};
-    kp.jobs = nullptr;
-    kp.job0 = jd;
-    kp.njobs = 1;
-    kp.chunk = chunk;
-    kp.queue = queue;
-    kp.total_items = (M + per_item - 1) / per_item;
     kp.hist = hist;
     kp.hist_over = hist_over;
-    const int grid = (int)std::min<long long>(grid_cap, kp.total_items);
-    void* args[] = {&kp};
-    s = launch((const void*)fn, dim3(grid), dim3(kWG), args, st);
+    s = launch_transform(jd, hist ? (int)kHist : mode_of(layout), tun, cus, queue, st, &kp);
     if (s || !hist) return s;
     // the pass for |W|/2 >= kHistBins - 1 (returns at once when there is none)
+    const int p = (tun && tun->split_p) ? tun->split_p : default_split(n);
     KFn fnb = lookup_kernel(n, n <= 8 ? n : p, kHistBig);
     if (!fnb) return fail(SBOX_ERR_INVALID_ARG, "no histogram kernel for n=%d", n);
     int occb = 1;
@@ -716,7 +776,7 @@ sbox_status plan_batch(const sbox_job* jobs, int count, const sbox_tuning* tun, 
       d.m = j.m;
       const bool sparse = mc && fp4_words(j.n, tun);
       d.nwords = sparse ? 256 : (j.n >= 5 ? 1 << (j.n - 5) : 1);
-      d.flags = sparse ? kWordsFp4 : 0;
+      d.flags = (sparse ? kWordsFp4 : 0) | (base_layout(j.layout) == 2 ? kSpecAMajor : 0);
       d.s_elem_bytes = j.s_elem_bytes;
       d.wscale = wscale_of(j.layout);
       const long long per_item = (long long)groups * c.chunk;
@@ -760,32 +820,21 @@ sbox_status launch_batch(const BatchLayout& L, void* ws, hipStream_t st, const C
   int* queue = reinterpret_cast<int*>(ws);
   const JobDesc* dtab = reinterpret_cast<const JobDesc*>(reinterpret_cast<char*>(ws) + kQueueBytes);
   sbox_status s;
-  // bit-slice every table (grid.y <= 65535 jobs per launch): waves of 64
-  // threads striding over a job's words, one per 256 words of the largest
-  // job (one up to n = 13); idle workgroups would only cost dispatch time
+  // bit-slice every table and set every job's start values (grid.y <= 65535
+  // jobs per launch; the first launch also zeroes the queue counters): waves
+  // of 64 threads striding over a job's words, one per 256 words of the
+  // largest job (one up to n = 13); idle workgroups would only cost dispatch
+  // time.  (One launch where there were a bit-slicing launch, an init launch
+  // per size class and a counter reset.)
   int maxw = 1;
   for (const JobDesc& jd : L.descs) maxw = std::max(maxw, jd.nwords);
   const unsigned gx = (unsigned)std::min(32, (maxw + 255) / 256);
   for (int j0 = 0; j0 < L.count; j0 += 65535) {
     const int nj = std::min(65535, L.count - j0);
     const JobDesc* d = dtab + j0;
-    void* args[] = {(void*)&d};
-    s = launch((const void*)&k_bitslice_jobs, dim3(gx, nj), dim3(64), args, st);
-    if (s) return s;
-  }
-  // per-job init (NL start value, maxabs[0], b = 0 spectrum row), then the queue counters
-  for (const ClassLaunch& c : L.classes) {
-    const JobDesc* d = reinterpret_cast<const JobDesc*>(reinterpret_cast<const char*>(dtab) + c.desc_off);
-    JobDesc unused{};
-    int njc = c.njobs, nq0 = 0, lay = base_layout(c.layout);
-    void* args[] = {(void*)&d, &unused, &njc, &queue, &nq0, &lay};
-    s = launch((const void*)&k_init_jobs, dim3(njc), dim3(256), args, st);
-    if (s) return s;
-  }
-  {
-    long long cnt = 64;
-    void* args[] = {&queue, &cnt};
-    s = launch((const void*)&k_zero, dim3(1), dim3(256), args, st);
+    int nq = j0 == 0 ? 64 : 0;
+    void* args[] = {(void*)&d, &queue, &nq};
+    s = launch((const void*)&k_prep_jobs, dim3(gx, nj), dim3(64), args, st);
     if (s) return s;
   }
   const bool fork = cs && L.classes.size() > 1 && cs->side.size() + 1 >= L.classes.size();
@@ -945,7 +994,9 @@ size_t sbox_walsh_nl_workspace_bytes(int n, int m, int layout) {
   if (!layout_valid(layout)) return 0;
   layout = base_layout(layout);
   if (layout != 0 && n + m > 34) return 0;
-  if (n <= 16) return kQueueBytes + f_bytes(n, m) + (use_slab(n, m, layout) ? slab_bytes(n, m) : 0);
+  if (n <= 16)
+    return kQueueBytes + f_bytes(n, m) + (use_slab(n, m, layout) ? slab_bytes(n, m) : 0) +
+           (use_perm_route(n, m, layout) ? perm_route_bytes(n) : 0);
   if (use_big(n, layout)) return big_bytes(n, m);
   return large_bytes(n, m, default_large_batch(n, m));
 }

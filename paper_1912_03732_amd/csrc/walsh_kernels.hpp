@@ -92,6 +92,7 @@ struct JobDesc {
 
 // JobDesc::flags
 constexpr int kWordsFp4 = 1;
+constexpr int kSpecAMajor = 2;  // spec is a-major (else b-major): where the batched start values go
 
 struct KParams {
   const JobDesc* jobs;   // device job table, or null to use job0
@@ -110,12 +111,32 @@ struct KParams {
   long long rows;        // ... and only rows [0, rows) exist there (0: all 2^m)
   unsigned long long* hist;  // histogram modes: [2^(n-1) + 1] counts of |W|/2
   unsigned long long* hist_over;  // values past the LDS bins seen by the counting pass
+  const int* gate;       // if set, the launch does nothing unless *gate == gate_run
+  int gate_run;
 };
 
 // The host passes these structs by value as kernel arguments; both
 // compilation passes (host and gfx950) must see the same layout.
 static_assert(sizeof(JobDesc) == 72 && alignof(JobDesc) == 8, "JobDesc layout");
-static_assert(sizeof(KParams) == 168 && __builtin_offsetof(KParams, hist_over) == 160, "KParams layout");
+static_assert(sizeof(KParams) == 184 && __builtin_offsetof(KParams, gate_run) == 176, "KParams layout");
+
+// A gated launch returns at once unless an earlier launch of the same call
+// left *gate == gate_run (a choice between two routes taken on the device).
+__device__ __forceinline__ bool gated_off(const KParams& kp) { return kp.gate && *kp.gate != kp.gate_run; }
+
+// The next work item of this workgroup from the queue counter, in the order
+// workgroups ask (workgroup-uniform, kept scalar).  The barriers also keep
+// the previous item's LDS use apart from this one's.  (A fixed assignment,
+// workgroup g taking items g, g + G, ..., with no atomic, was measured
+// slower for every single-box workload, e.g. 16 x 16 fused 0.589 ->
+// 0.626 ms: workgroups that start late or run slower are not evened out.)
+__device__ __forceinline__ long long next_item(const KParams& kp, long long* s_item) {
+  if (tid_x() == 0) *s_item = (long long)atomicAdd(kp.queue, 1);
+  __syncthreads();
+  const long long item = __builtin_amdgcn_readfirstlane((int)*s_item);
+  __syncthreads();
+  return item;
+}
 
 typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));
 typedef __attribute__((address_space(1))) int32_t gint32;  // global memory
@@ -265,6 +286,32 @@ __device__ __forceinline__ int group_reduce(int v) {
   return v;
 }
 __device__ __forceinline__ int wave_max(int v) { return group_reduce<64, true>(v); }
+__device__ __forceinline__ int wave_min(int v) { return group_reduce<64, false>(v); }
+
+// NL = the minimum over a box's masks of 2^(n-1) - max|W|/2, taken with
+// atomicMin.  The memory system serialises device-scope atomics on one
+// address (about 10 ns apart: a 12 x 12 call took 20.6 / 33 / 59 us with
+// 1,024 / 2,048 / 4,096 of them), so the kernels issue few: a launch over
+// one box keeps each lane's candidate over all its items and adds one
+// value per workgroup when it ends; a batched launch, whose consecutive
+// items belong to different boxes, adds one value per wave and item.
+// (12 x 12 fused 20.6 -> 12.3 us, 12 x 20 0.408 -> 0.375 ms, the 4096-box
+// batch 0.86 -> 0.82 ms.)  Kernels whose workgroup works on one mask at a
+// time (n = 16) keep one add per item, which is one atomic already.  Lanes
+// without a candidate hold 0x7fffffff.
+__device__ __forceinline__ void nl_add_wave(int32_t* nl, int v) {
+  v = wave_min(v);
+  if ((tid_x() & 63) == 0 && v != 0x7fffffff) atomicMin(nl, v);
+}
+__device__ __forceinline__ void nl_add_workgroup(int32_t* nl, int v) {
+  __shared__ int s_min;
+  v = wave_min(v);
+  if (tid_x() == 0) s_min = 0x7fffffff;
+  __syncthreads();
+  if ((tid_x() & 63) == 0 && v != 0x7fffffff) atomicMin(&s_min, v);
+  __syncthreads();
+  if (tid_x() == 0 && s_min != 0x7fffffff) atomicMin(nl, s_min);
+}
 
 // ---------------------------------------------------------------------------
 // Main fused kernel, n <= 16 (MODE kBlock: one 2^16 block of a larger n).
@@ -280,6 +327,7 @@ constexpr int min_blocks() {
 
 template <int N, int P_, int MODE>
 __global__ __launch_bounds__(kWG, (min_blocks<N, P_, MODE>())) void k_walsh(const KParams kp) {
+  if (gated_off(kp)) return;
   constexpr int P = (N <= 8) ? N : P_;
   constexpr int Q = N - P;
   static_assert(Q >= 0 && Q <= P, "bad split");
@@ -321,12 +369,10 @@ __global__ __launch_bounds__(kWG, (min_blocks<N, P_, MODE>())) void k_walsh(cons
   const int lane = tid & 63;
   const int C = kp.chunk;
 
+  // NL candidate of this lane: per item in a batch, over all its items for one box
+  int runmin = 0x7fffffff;
   for (;;) {
-    if (tid == 0) s_item = (long long)atomicAdd(kp.queue, 1);
-    __syncthreads();
-    // the item is workgroup-uniform: keep it (and what derives from it) scalar
-    const long long item = __builtin_amdgcn_readfirstlane((int)s_item);
-    __syncthreads();
+    const long long item = next_item(kp, &s_item);
     if (item >= kp.total_items) break;
 
     // ---- decode the item
@@ -353,7 +399,6 @@ __global__ __launch_bounds__(kWG, (min_blocks<N, P_, MODE>())) void k_walsh(cons
     const long long kend = (kp.kcount > 0) ? (kp.kbase + kp.kcount) : (1LL << jd.m);
     const long long wb = (MODE == kBlock ? ((long long)xblk << 11) : 0) + (long long)tg * NW;
     const int n = jd.n;
-    int runmin = 0x7fffffff;
     uint32_t G[NW], Fn[NW];
 
     for (int step = 0; step < C; ++step) {
@@ -625,7 +670,13 @@ __global__ __launch_bounds__(kWG, (min_blocks<N, P_, MODE>())) void k_walsh(cons
       }
     }
     if constexpr (MODE != kBlock && MODE != kHistBig) {
-      if (tg == 0 && runmin != 0x7fffffff) atomicMin(jd.nl, runmin);
+      if (GPW == 1) {  // one thread group a workgroup: one add an item (deferring it measured slower at n = 16)
+        if (tg == 0 && runmin != 0x7fffffff) atomicMin(jd.nl, runmin);
+        runmin = 0x7fffffff;
+      } else if (kp.jobs != nullptr) {
+        nl_add_wave(jd.nl, runmin);
+        runmin = 0x7fffffff;
+      }
     }
     if constexpr (MODE == kHist) {
       // keep every LDS count below 2^32
@@ -637,6 +688,8 @@ __global__ __launch_bounds__(kWG, (min_blocks<N, P_, MODE>())) void k_walsh(cons
       }
     }
   }
+  if constexpr (MODE != kBlock && MODE != kHistBig && GPW > 1)
+    if (kp.jobs == nullptr) nl_add_workgroup(kp.job0.nl, runmin);
   if constexpr (MODE == kHist) {
     __syncthreads();
     hist_flush();
@@ -704,6 +757,7 @@ __device__ __forceinline__ f16x8 as_f16x8(uint32_t r0, uint32_t r1, uint32_t r2,
 
 template <int ROUNDS>
 __global__ __launch_bounds__(kWG, ROUNDS) void k_walsh_mfma16(const KParams kp) {
+  if (gated_off(kp)) return;
   constexpr int NW = 8;
   constexpr int TPR = 8 / ROUNDS;              // a' & 7 values per round
   constexpr int LDSW = 4 * TPR * 4 * 4 * 64;   // dest wave x (a' & 7) x v x source wave x lane
@@ -735,10 +789,7 @@ __global__ __launch_bounds__(kWG, ROUNDS) void k_walsh_mfma16(const KParams kp) 
   const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
 
   for (;;) {
-    if (tid == 0) s_item = (long long)atomicAdd(kp.queue, 1);
-    __syncthreads();
-    const long long item = __builtin_amdgcn_readfirstlane((int)s_item);
-    __syncthreads();
+    const long long item = next_item(kp, &s_item);
     if (item >= kp.total_items) break;
     JobDesc jd;
     long long li;
@@ -868,6 +919,7 @@ __global__ __launch_bounds__(kWG, ROUNDS) void k_walsh_mfma16(const KParams kp) 
         // first barrier, which wave 0 reaches only after these reads
       }
     }
+    // a workgroup works on one mask at a time: already one add an item
     if (tid == 0 && runmin != 0x7fffffff) atomicMin(jd.nl, runmin);
   }
 }
@@ -932,6 +984,7 @@ constexpr int kMxHistBins = 1536;
 
 template <int CPR, bool HIST = false>
 __global__ __launch_bounds__(kWG, (mx_min_waves<CPR>())) void k_walsh_mx16(const KParams kp) {
+  if (gated_off(kp)) return;
   constexpr int NW = 8;
   constexpr int ROUNDS = 8 / CPR;
   constexpr int SLOT = mx_slot_words<CPR>();
@@ -994,10 +1047,7 @@ __global__ __launch_bounds__(kWG, (mx_min_waves<CPR>())) void k_walsh_mx16(const
   const int rslot = ((wave * 4 + g) * 16 + col) * SLOT;
 
   for (;;) {
-    if (tid == 0) s_item = (long long)atomicAdd(kp.queue, 1);
-    __syncthreads();
-    const long long item = __builtin_amdgcn_readfirstlane((int)s_item);
-    __syncthreads();
+    const long long item = next_item(kp, &s_item);
     if (item >= kp.total_items) break;
     JobDesc jd;
     long long li;
@@ -1148,6 +1198,7 @@ __global__ __launch_bounds__(kWG, (mx_min_waves<CPR>())) void k_walsh_mx16(const
         }
       }
     }
+    // a workgroup works on one mask at a time: already one add an item
     if (tid == 0 && runmin != 0x7fffffff) atomicMin(jd.nl, runmin);
     if constexpr (HIST) {
       // keep every LDS count below 2^32
@@ -1191,6 +1242,7 @@ __global__ __launch_bounds__(kWG, (mx_min_waves<CPR>())) void k_walsh_mx16(const
 typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
 
 __global__ __launch_bounds__(kWG, 4) void k_walsh_mfma12(const KParams kp) {
+  if (gated_off(kp)) return;
   constexpr int NW = 2;
   constexpr int GPW = kWG / 64;               // masks (waves) per workgroup
   __shared__ uint32_t lds[GPW * 32 * 68];     // 8.5 KiB per wave: 32 rows of 68 words
@@ -1223,11 +1275,10 @@ __global__ __launch_bounds__(kWG, 4) void k_walsh_mfma12(const KParams kp) {
   const int xs = lane & 3;                                  // x6, x7
   const int dl0 = ((lane >> 2) & 3) | (((lane >> 4) & 3) << 4);  // x8, x9, x10, x11
 
+  // NL candidate of this lane: per item in a batch, over all its items for one box
+  int runmin = 0x7fffffff;
   for (;;) {
-    if (tid == 0) s_item = (long long)atomicAdd(kp.queue, 1);
-    __syncthreads();
-    const long long item = __builtin_amdgcn_readfirstlane((int)s_item);
-    __syncthreads();
+    const long long item = next_item(kp, &s_item);
     if (item >= kp.total_items) break;
     JobDesc jd;
     long long li;
@@ -1247,7 +1298,6 @@ __global__ __launch_bounds__(kWG, 4) void k_walsh_mfma12(const KParams kp) {
     const long long kend = 1LL << jd.m;
     const long long wb = (long long)lane * NW;
     const int n = jd.n;
-    int runmin = 0x7fffffff;
     uint32_t G[NW], Fn[NW];
 
     for (int step = 0; step < C; ++step) {
@@ -1310,8 +1360,12 @@ __global__ __launch_bounds__(kWG, 4) void k_walsh_mfma12(const KParams kp) {
         runmin = min(runmin, (1 << (n - 1)) - mx);
       }
     }
-    if (lane == 0 && runmin != 0x7fffffff) atomicMin(jd.nl, runmin);
+    if (kp.jobs != nullptr) {
+      nl_add_wave(jd.nl, runmin);
+      runmin = 0x7fffffff;
+    }
   }
+  if (kp.jobs == nullptr) nl_add_workgroup(kp.job0.nl, runmin);
 }
 
 // ---------------------------------------------------------------------------
@@ -1336,6 +1390,7 @@ __global__ __launch_bounds__(kWG, 4) void k_walsh_mfma12(const KParams kp) {
 // Every bit of x is transformed once (7 + 5).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kWG, 3) void k_walsh_mx12(const KParams kp) {
+  if (gated_off(kp)) return;
   constexpr int NW = 4;
   constexpr int GPW = kWG / 64;  // masks (waves) per workgroup
   __shared__ long long s_item;
@@ -1365,11 +1420,10 @@ __global__ __launch_bounds__(kWG, 3) void k_walsh_mx12(const KParams kp) {
   const f32x4 cfix = {fix, fix, fix, fix};
   const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
 
+  // NL candidate of this lane: per item in a batch, over all its items for one box
+  int runmin = 0x7fffffff;
   for (;;) {
-    if (tid == 0) s_item = (long long)atomicAdd(kp.queue, 1);
-    __syncthreads();
-    const long long item = __builtin_amdgcn_readfirstlane((int)s_item);
-    __syncthreads();
+    const long long item = next_item(kp, &s_item);
     if (item >= kp.total_items) break;
     JobDesc jd;
     long long li;
@@ -1389,7 +1443,6 @@ __global__ __launch_bounds__(kWG, 3) void k_walsh_mx12(const KParams kp) {
     const long long kend = 1LL << jd.m;
     const long long wb = (long long)lane * NW;
     const int n = jd.n;
-    int runmin = 0x7fffffff;
     uint32_t G[NW], Fn[NW];
 
     for (int step = 0; step < C; ++step) {
@@ -1441,8 +1494,12 @@ __global__ __launch_bounds__(kWG, 3) void k_walsh_mx12(const KParams kp) {
         runmin = min(runmin, (1 << (n - 1)) - mx);
       }
     }
-    if (lane == 0 && runmin != 0x7fffffff) atomicMin(jd.nl, runmin);
+    if (kp.jobs != nullptr) {
+      nl_add_wave(jd.nl, runmin);
+      runmin = 0x7fffffff;
+    }
   }
+  if (kp.jobs == nullptr) nl_add_workgroup(kp.job0.nl, runmin);
 }
 
 // ---------------------------------------------------------------------------
@@ -1470,6 +1527,7 @@ __device__ __forceinline__ uint32_t i8_sign_word(int kbase, int a) {
 }
 
 __global__ __launch_bounds__(kWG, 3) void k_walsh_i8x12(const KParams kp) {
+  if (gated_off(kp)) return;
   constexpr int NW = 4;
   constexpr int GPW = kWG / 64;  // masks (waves) per workgroup
   constexpr uint32_t kFlip = 0xFEFEFEFEu;  // +1 <-> -1 in every byte
@@ -1505,11 +1563,10 @@ __global__ __launch_bounds__(kWG, 3) void k_walsh_i8x12(const KParams kp) {
   const i32x4 izero = {0, 0, 0, 0};
   const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
 
+  // NL candidate of this lane: per item in a batch, over all its items for one box
+  int runmin = 0x7fffffff;
   for (;;) {
-    if (tid == 0) s_item = (long long)atomicAdd(kp.queue, 1);
-    __syncthreads();
-    const long long item = __builtin_amdgcn_readfirstlane((int)s_item);
-    __syncthreads();
+    const long long item = next_item(kp, &s_item);
     if (item >= kp.total_items) break;
     JobDesc jd;
     long long li;
@@ -1529,7 +1586,6 @@ __global__ __launch_bounds__(kWG, 3) void k_walsh_i8x12(const KParams kp) {
     const long long kend = 1LL << jd.m;
     const long long wb = (long long)lane * NW;
     const int n = jd.n;
-    int runmin = 0x7fffffff;
     uint32_t G[NW], Fn[NW];
 
     for (int step = 0; step < C; ++step) {
@@ -1594,8 +1650,12 @@ __global__ __launch_bounds__(kWG, 3) void k_walsh_i8x12(const KParams kp) {
         runmin = min(runmin, (1 << (n - 1)) - mx);
       }
     }
-    if (lane == 0 && runmin != 0x7fffffff) atomicMin(jd.nl, runmin);
+    if (kp.jobs != nullptr) {
+      nl_add_wave(jd.nl, runmin);
+      runmin = 0x7fffffff;
+    }
   }
+  if (kp.jobs == nullptr) nl_add_workgroup(kp.job0.nl, runmin);
 }
 
 // ---------------------------------------------------------------------------
@@ -1882,9 +1942,39 @@ __global__ __launch_bounds__(256) void k_bitslice_big(const void* S, int L, int 
   }
 }
 
-// Batched: bid_y() selects the job, threads stride over its words.
-__global__ __launch_bounds__(64) void k_bitslice_jobs(const JobDesc* jobs) {
+// ---------------------------------------------------------------------------
+// Per-call initialisation: queue counters, NL start value 2^(n-1),
+// maxabs[0] = 2^n, and the b = 0 row / column of a requested spectrum.
+// ---------------------------------------------------------------------------
+// Entry a of the spectrum's b = 0 row (b-major) or column (a-major).
+__device__ __forceinline__ void init_spec_entry(const JobDesc& jd, long long a, int layout) {
+  const int v = (a == 0) ? (int)((1LL << jd.n) >> 1) * -jd.wscale : 0;  // 2^n (W) or 2^(n-1) (LAT)
+  if (layout == 1) jd.spec[a] = v;
+  else jd.spec[a << jd.m] = v;
+}
+
+// One workgroup's share: the job's start values (and, if `first`, the queue
+// counters); with `spec_row` false the caller writes the b = 0 row / column.
+__device__ __forceinline__ void init_job(const JobDesc& jd, bool first, int* queue, int nqueue, int layout,
+                                         bool spec_row = true) {
+  if (first) {
+    for (int i = tid_x(); i < nqueue; i += bdim_x()) queue[i] = 0;
+  }
+  if (tid_x() == 0) {
+    *jd.nl = 1 << (jd.n - 1);
+    if (jd.maxabs) jd.maxabs[0] = 1 << jd.n;
+  }
+  if (jd.spec && spec_row)
+    for (long long a = tid_x(); a < (1LL << jd.n); a += bdim_x()) init_spec_entry(jd, a, layout);
+}
+
+// Batched: bid_y() selects the job, threads stride over its words; the
+// first workgroup of a job also sets its start values (NL, maxabs[0], the
+// b = 0 row or column of a spectrum) and, for the launch's first job, zeroes
+// `nqueue` queue counters, so a batch starts with this one launch.
+__global__ __launch_bounds__(64) void k_prep_jobs(const JobDesc* jobs, int* queue, int nqueue) {
   const JobDesc jd = jobs[bid_y()];
+  if (bid_x() == 0) init_job(jd, bid_y() == 0, queue, nqueue, (jd.flags & kSpecAMajor) ? 2 : 1);
   for (int w = bid_x() * bdim_x() + tid_x(); w < jd.nwords; w += gdim_x() * bdim_x()) {
     if (jd.s_elem_bytes == 1) bitslice_job<1>(jd, w);
     else if (jd.s_elem_bytes == 2) bitslice_job<2>(jd, w);
@@ -2587,10 +2677,14 @@ __global__ void k_criteria_finish(int32_t* crit) {
 // the a-major matrix (scaled by wscale: W or W/2) through an LDS tile of 64
 // rows by 128 entries read as int16 pairs, so that the slab reads (along a)
 // and the spectrum writes (along b) are 256-byte runs.  Column b = 0 is
-// written by the init kernel and skipped here.
+// written by the init kernel and skipped here.  With `skip` set, the launch
+// does nothing when *skip != 0 (the box is a permutation, whose a-major
+// matrix the call writes another way).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_transpose_slab16(const int16_t* slab, int n, int32_t* spec, int m,
-                                                          long long b0, int B, int wscale, const void* S, int eb) {
+                                                          long long b0, int B, int wscale, const void* S, int eb,
+                                                          const int* skip) {
+  if (skip && *skip) return;
   __shared__ int32_t tile[64][65];  // tile[j][p]: entries a0 + 2p, a0 + 2p + 1 of row j
   const long long N = 1LL << n;
   const long long a0 = (long long)bid_x() * 128;
@@ -2618,30 +2712,7 @@ __global__ __launch_bounds__(256) void k_transpose_slab16(const int16_t* slab, i
   }
 }
 
-// ---------------------------------------------------------------------------
-// Per-call initialisation: queue counters, NL start value 2^(n-1),
-// maxabs[0] = 2^n, and the b = 0 row / column of a requested spectrum.
-// ---------------------------------------------------------------------------
-// One workgroup's share: the job's start values (and, for the first job, the
-// queue counters).
-__device__ __forceinline__ void init_job(const JobDesc& jd, bool first, int* queue, int nqueue, int layout) {
-  if (first) {
-    for (int i = tid_x(); i < nqueue; i += bdim_x()) queue[i] = 0;
-  }
-  if (tid_x() == 0) {
-    *jd.nl = 1 << (jd.n - 1);
-    if (jd.maxabs) jd.maxabs[0] = 1 << jd.n;
-  }
-  if (jd.spec) {
-    const long long N = 1LL << jd.n;
-    for (long long a = tid_x(); a < N; a += bdim_x()) {
-      const int v = (a == 0) ? (int)(N >> 1) * -jd.wscale : 0;  // 2^n (W) or 2^(n-1) (LAT)
-      if (layout == 1) jd.spec[a] = v;
-      else jd.spec[a << jd.m] = v;
-    }
-  }
-}
-
+// Start values of a call without its own preparation launch (n > 16).
 __global__ __launch_bounds__(256) void k_init_jobs(const JobDesc* jobs, JobDesc job0, int njobs,
                                                    int* queue, int nqueue, int layout) {
   const int j = bid_x();
@@ -2651,20 +2722,66 @@ __global__ __launch_bounds__(256) void k_init_jobs(const JobDesc* jobs, JobDesc 
 
 // A single box in one launch before its transform: workgroup 0 sets the
 // start values, the others bit-slice the table into jd.F (dense words from
-// n = 6 on: a wave per 64 entries; else a word a thread).
+// n = 6 on: a wave per 64 entries, which also write those entries of the
+// spectrum's b = 0 row or column, a column being one cache line an entry;
+// else a word a thread).
 template <int EB>
 __global__ __launch_bounds__(256) void k_prep_single(JobDesc jd, int* queue, int nqueue, int layout) {
+  const bool dense = jd.n >= 6 && !(jd.flags & kWordsFp4);
   if (bid_x() == 0) {
-    init_job(jd, true, queue, nqueue, layout);
+    init_job(jd, true, queue, nqueue, layout, !dense);
     return;
   }
-  if (jd.n >= 6 && !(jd.flags & kWordsFp4)) {  // dense words: a wave per 64 entries
+  if (dense) {  // a wave per 64 entries
     const long long x0 = ((long long)(bid_x() - 1) * bdim_x() + (tid_x() & ~63));
-    if (x0 < (1LL << jd.n)) bitslice_wave<EB>(jd.S, jd.m, const_cast<uint32_t*>(jd.F), jd.nwords, x0);
+    if (x0 < (1LL << jd.n)) {
+      if (jd.spec) init_spec_entry(jd, x0 + (tid_x() & 63), layout);
+      bitslice_wave<EB>(jd.S, jd.m, const_cast<uint32_t*>(jd.F), jd.nwords, x0);
+    }
     return;
   }
   const int w = (bid_x() - 1) * bdim_x() + tid_x();
   if (w < jd.nwords) bitslice_job<EB>(jd, w);
+}
+
+// ---------------------------------------------------------------------------
+// a-major spectrum of a permutation (n = m).  Substituting y = S(x) in the
+// sum of Eq. 1 gives W_{S^-1}(u, v) = W_S(v, u): the spectrum of the inverse
+// map is the transpose, so row a of the a-major matrix of S is row a of the
+// b-major matrix of S^-1, which the b-major store mode writes as whole rows,
+// with no slab and no transpose.  Whether S is a permutation is found on the
+// device, so that the call stays asynchronous and capturable: the scatter
+// writes inv[S(x)] = x and sets *bij = 1; the check clears *bij if some y
+// has S(inv[y]) != y, which (with n = m) happens exactly when S is not onto.
+// Later launches of the call read *bij and either run or return at once.
+// ---------------------------------------------------------------------------
+template <int EB>
+__global__ __launch_bounds__(256) void k_perm_scatter(const void* S, int n, uint16_t* inv, int* bij) {
+  const uint32_t x = bid_x() * bdim_x() + tid_x();
+  if (x == 0) *bij = 1;
+  if (x < (1u << n)) inv[load_entry<EB>(S, x) & ((1u << n) - 1)] = (uint16_t)x;
+}
+
+// The check, then the start values of the b-major job of S^-1 (workgroup 0:
+// its NL start value and row 0, W_{S^-1}(u, 0) = 2^n [u = 0], which is row
+// a = 0 of the a-major matrix of S) and its bit-sliced words (the other
+// workgroups, a wave per 64 entries of inv).  Row 0 is written either way:
+// if S is not a permutation, the transposed slabs overwrite every entry
+// but the first, which is 2^n for every S.
+template <int EB>
+__global__ __launch_bounds__(256) void k_perm_check_prep(const void* S, JobDesc jinv, int* bij, int* queue,
+                                                         int nqueue) {
+  if (bid_x() == 0) {
+    init_job(jinv, true, queue, nqueue, 1);
+    return;
+  }
+  const long long y0 = (long long)(bid_x() - 1) * bdim_x() + (tid_x() & ~63);
+  if (y0 >= (1LL << jinv.n)) return;
+  const uint32_t y = (uint32_t)y0 + (tid_x() & 63);
+  // an entry no x was scattered to holds an old value: masked to stay inside S
+  const uint32_t x = reinterpret_cast<const uint16_t*>(jinv.S)[y] & ((1u << jinv.n) - 1);
+  if ((load_entry<EB>(S, x) & ((1u << jinv.m) - 1)) != y) *bij = 0;
+  bitslice_wave<2>(jinv.S, jinv.m, const_cast<uint32_t*>(jinv.F), jinv.nwords, y0);
 }
 
 // Zero `count` ints (queue counters, per-batch maxima) without a memset node.
