@@ -751,14 +751,14 @@ sbox_status plan_batch(const sbox_job* jobs, int count, const sbox_tuning* tun, 
     for (int k = i; k < jend; ++k) masks_total += 1LL << jobs[order[k]].m;
     pick_chunk(masks_total, groups, grid_cap, tun ? tun->chunk : 0, &c.chunk);
     if (!(tun && tun->chunk) && n > 8 && jend - i >= 32) {
-      // a class of many boxes: long items (64 masks per group, a power of two
+      // a class of many boxes: long items (128 masks per group, a power of two
       // so items tile every box's 2^m masks) as long as the queue still holds
       // an item for every workgroup; each item rebuilds its first mask from up
       // to m slices and takes a queue atomic and a job search (n = 10 class of
       // the 4096-box mix: 0.39 -> 0.21 ms, n = 12: 1.10 -> 0.96 ms; the whole
-      // batch at 16 / 32 / 64 masks: 0.847 / 0.819 / 0.804 ms).  A few large
-      // boxes keep the balance rule: long items leave a tail there.
-      int cb = 64;
+      // batch at 16 / 32 / 64 / 128 masks: 0.847 / 0.819 / 0.804 / 0.791 ms).
+      // A few large boxes keep the balance rule: long items leave a tail there.
+      int cb = 128;
       while (cb > 4 && masks_total / ((long long)groups * cb) < grid_cap) cb >>= 1;
       c.chunk = cb;
     }
