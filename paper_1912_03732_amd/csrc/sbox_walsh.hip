@@ -411,9 +411,13 @@ sbox_status run_single(const void* S, int n, int m, int eb, int32_t* maxabs, int
   jd.s_elem_bytes = eb;
   jd.wscale = wscale;
   jd.flags = sparse ? kWordsFp4 : 0;
-  // one launch: start values (queue counters, NL, maxabs[0], b = 0 spectrum
-  // row) in workgroup 0, bit-sliced component words in the others
-  {
+  if (n >= 6 && n <= 8 && m <= 8 && !hist) {
+    // the transform is one workgroup (a thread a mask), which prepares the
+    // box itself: the call is one launch
+    jd.flags |= kPrepInline;
+  } else {
+    // one launch: start values (queue counters, NL, maxabs[0], b = 0 spectrum
+    // row) in workgroup 0, bit-sliced component words in the others
     int nq = 64, lay = layout;
     void* args[] = {&jd, &queue, &nq, &lay};
     const void* fn = eb == 1 ? (const void*)&k_prep_single<1> : eb == 2 ? (const void*)&k_prep_single<2>

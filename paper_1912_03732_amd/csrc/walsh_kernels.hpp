@@ -93,6 +93,7 @@ struct JobDesc {
 // JobDesc::flags
 constexpr int kWordsFp4 = 1;
 constexpr int kSpecAMajor = 2;  // spec is a-major (else b-major): where the batched start values go
+constexpr int kPrepInline = 4;  // a one-workgroup launch (n <= 8) prepares its box itself
 
 struct KParams {
   const JobDesc* jobs;   // device job table, or null to use job0
@@ -123,6 +124,12 @@ static_assert(sizeof(KParams) == 184 && __builtin_offsetof(KParams, gate_run) ==
 // A gated launch returns at once unless an earlier launch of the same call
 // left *gate == gate_run (a choice between two routes taken on the device).
 __device__ __forceinline__ bool gated_off(const KParams& kp) { return kp.gate && *kp.gate != kp.gate_run; }
+
+// Defined with the preparation kernels below.
+__device__ __forceinline__ void init_job(const JobDesc& jd, bool first, int* queue, int nqueue, int layout,
+                                         bool spec_row = true);
+template <int EB>
+__device__ void bitslice_wave(const void* S, int m, uint32_t* F, int nwords, long long x0);
 
 // The next work item of this workgroup from the queue counter, in the order
 // workgroups ask (workgroup-uniform, kept scalar).  The barriers also keep
@@ -363,6 +370,27 @@ __global__ __launch_bounds__(kWG, (min_blocks<N, P_, MODE>())) void k_walsh(cons
     for (int k = tid; k < kHistBins; k += kWG) hl[k] = 0;  // ordered by the loop's first barrier
   if constexpr (MODE == kHistBig)
     if (*kp.hist_over == 0) return;  // no large value: nothing to add
+  // A launch that is one workgroup over a whole small box (6 <= n <= 8, at
+  // most 256 masks, one item) bit-slices the table (a wave per 64 entries,
+  // a ballot per output bit) and sets the call's start values itself, so the
+  // call is this one launch; it zeroes its queue counter too, from which
+  // thread 0 then takes the item.  The barrier makes the words visible to
+  // the workgroup.
+  if constexpr (N >= 6 && N <= 8 && (MODE == kMax || MODE == kStoreB || MODE == kStoreA)) {
+    if (kp.job0.flags & kPrepInline) {
+      const JobDesc& j0 = kp.job0;
+      if (tid == 0) *kp.queue = 0;
+      init_job(j0, false, nullptr, 0, MODE == kStoreA ? 2 : 1);
+      const long long x0 = tid & ~63;
+      if (x0 < (1 << N)) {
+        uint32_t* F = const_cast<uint32_t*>(j0.F);
+        if (j0.s_elem_bytes == 1) bitslice_wave<1>(j0.S, j0.m, F, j0.nwords, x0);
+        else if (j0.s_elem_bytes == 2) bitslice_wave<2>(j0.S, j0.m, F, j0.nwords, x0);
+        else bitslice_wave<4>(j0.S, j0.m, F, j0.nwords, x0);
+      }
+      __syncthreads();
+    }
+  }
   // thread group in this workgroup (wave-uniform when a group spans whole waves)
   const int g = (Q >= 6) ? __builtin_amdgcn_readfirstlane(tid >> Q) : (tid >> Q);
   const int tg = tid & ((1 << Q) - 1);    // thread within the group
@@ -1956,7 +1984,7 @@ __device__ __forceinline__ void init_spec_entry(const JobDesc& jd, long long a, 
 // One workgroup's share: the job's start values (and, if `first`, the queue
 // counters); with `spec_row` false the caller writes the b = 0 row / column.
 __device__ __forceinline__ void init_job(const JobDesc& jd, bool first, int* queue, int nqueue, int layout,
-                                         bool spec_row = true) {
+                                         bool spec_row) {
   if (first) {
     for (int i = tid_x(); i < nqueue; i += bdim_x()) queue[i] = 0;
   }

@@ -596,3 +596,25 @@ def test_fp4_matrix_core_variant_12(m, kind, variant):
 def test_fp4_matrix_core_12_launch_shapes(chunk, grid, variant):
     S = table(12, 11, 16600 + chunk)
     check_against_oracle(S, 12, 11, nthreads=NT, tuning=B.sbox_tuning(0, chunk, grid, variant))
+
+
+@pytest.mark.parametrize("n,m", [(6, 6), (7, 5), (8, 8), (8, 1)])
+def test_one_launch_small_boxes_reuse_workspace(n, m):
+    """6 <= n <= 8 with at most 256 masks: the transform launch prepares the
+    box itself (bit-slicing, start values, its queue counter).  Calls on one
+    workspace, alternating with a larger box that uses the preparation
+    launch, each give the oracle's spectrum, maxima and NL in all three
+    layouts."""
+    ws = B.Workspace(B.sbox_walsh_nl_workspace_bytes(10, 10, B.SPECTRUM_A_MAJOR))
+    g = inputs.rng(15400 + 16 * n + m)
+    big = inputs.random_function(10, 10, g)
+    for rep in range(3):
+        S = inputs.permutation(n, g) if n == m else inputs.random_function(n, m, g)
+        for spectrum, lay in ((None, None), ("b", oracle.B_MAJOR), ("a", oracle.A_MAJOR)):
+            nl, mx, spec = B.walsh_nl(dev_table(S, m), n, m, spectrum=spectrum, workspace=ws)
+            onl, omx = oracle.walsh_nl(S, n, m)
+            assert nl == onl and np.array_equal(mx.cpu().numpy(), omx), (rep, spectrum)
+            if spectrum:
+                assert np.array_equal(spec.cpu().numpy(), oracle.spectrum(S, n, m, lay)), (rep, spectrum)
+        bnl, _, _ = B.walsh_nl(dev_table(big, 10), 10, 10, workspace=ws)
+        assert bnl == oracle.walsh_nl(big, 10, 10)[0]

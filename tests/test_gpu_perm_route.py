@@ -141,3 +141,4 @@ def test_graph_replay_switches_route():
         assert np.array_equal(mx.cpu().numpy(), rmx), (rep, key)
     del spec
     torch.cuda.empty_cache()
+
