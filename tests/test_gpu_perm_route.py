@@ -69,33 +69,36 @@ def test_affine_permutation_14():
     _full_check(S, n, "a", True)
 
 
-@pytest.mark.parametrize("kind", ["perm", "not", "affine"])
+@pytest.mark.parametrize("kind", ["perm", "not", "affine", "affine-lat"])
 def test_15_and_16_sampled(kind):
     """n = m = 15 and 16: sampled columns and rows against the oracle, and
     for a permutation Parseval over b on the first 4096 rows a (row a of S's
     matrix is the spectrum of the component a . S^-1).  The affine map
-    x -> x ^ c reaches |W| = 2^n, at n = 16 one past the int16 range."""
+    x -> x ^ c reaches |W| = 2^n, at n = 16 one past the int16 range, also
+    as the LAT (W/2)."""
     import torch
     perm = kind != "not"
+    lat = kind.endswith("-lat")
     for n in (15, 16):
         S = inputs.permutation(n, inputs.rng(15200 + n))
         if kind == "not":
             S = _not_onto(S, 15210 + n)
-        if kind == "affine":
+        if kind.startswith("affine"):
             S = (np.arange(1 << n) ^ (0x5A3C & ((1 << n) - 1))).astype(np.uint16)
-        nl, mx, spec = B.walsh_nl(dev_table(S, n), n, n, spectrum="a")
+        nl, mx, spec = B.walsh_nl(dev_table(S, n), n, n, spectrum="lat-a" if lat else "a")
+        div = 2 if lat else 1
         g = inputs.rng(15220 + n)
         for b in [0, 1, (1 << n) - 1] + [int(v) for v in g.integers(1, 1 << n, size=4)]:
             col = spec[:, b].cpu().numpy()
-            ref = oracle.walsh_column(S, n, n, b)
+            ref = oracle.walsh_column(S, n, n, b) // div
             assert np.array_equal(col, ref), (n, kind, b, first_diff(col, ref))
         for a in [0, 1, (1 << n) - 1, int(g.integers(2, 1 << n))]:
             row = spec[a, ::257].cpu().numpy()
-            ref = np.array([oracle.walsh_entry(S, n, a, b) for b in range(0, 1 << n, 257)])
+            ref = np.array([oracle.walsh_entry(S, n, a, b) for b in range(0, 1 << n, 257)]) // div
             assert np.array_equal(row, ref), (n, kind, a, first_diff(row, ref))
         if perm:
             sq = spec[:4096].to(torch.float64).square().sum(dim=1)
-            assert bool((sq == float(1 << (2 * n))).all())
+            assert bool((sq == float(1 << (2 * n)) / (div * div)).all())
         onl, omx = oracle.walsh_nl(S, n, n, nthreads=NT)
         assert nl == onl
         assert np.array_equal(mx.cpu().numpy(), omx)
