@@ -56,6 +56,24 @@ def test_large_n_workspace_grows_with_n(lib):
     assert B.sbox_walsh_nl_workspace_bytes(20, 16, 0) > B.sbox_walsh_nl_workspace_bytes(17, 16, 0) > 0
 
 
+@pytest.mark.parametrize("n", [12, 13, 14, 15, 16])
+def test_a_major_workspace_holds_the_inverse_route(lib, n):
+    """An a-major spectrum (or LAT) with n = m >= 14 also holds the inverse
+    table (uint16), its bit-sliced words and a flag beside the slab; the
+    b-major layout, non-square boxes and n = m < 14 do not."""
+    a = B.sbox_walsh_nl_workspace_bytes(n, n, B.SPECTRUM_A_MAJOR)
+    assert a == B.sbox_walsh_nl_workspace_bytes(n, n, B.LAT_A_MAJOR)
+    b = B.sbox_walsh_nl_workspace_bytes(n, n, B.SPECTRUM_B_MAJOR)
+    slab = min(1 << n, max(64, (1 << 27) >> n)) * (1 << n) * 2   # int16 rows of 2^27 entries at most
+    route = 256 + (2 << n) + n * (1 << (n - 3))                   # flag, inverse table, its words
+    assert a - b == slab + (route if n >= 14 else 0)
+    # non-square boxes take the slab only
+    if n <= 15:
+        a1 = B.sbox_walsh_nl_workspace_bytes(n, n + 1, B.SPECTRUM_A_MAJOR)
+        b1 = B.sbox_walsh_nl_workspace_bytes(n, n + 1, B.SPECTRUM_B_MAJOR)
+        assert a1 - b1 == min(1 << (n + 1), max(64, (1 << 27) >> n)) * (1 << n) * 2
+
+
 @pytest.mark.parametrize("args,status", [
     (dict(n=0, m=4), B.SBOX_ERR_UNSUPPORTED),
     (dict(n=4, m=25), B.SBOX_ERR_UNSUPPORTED),
