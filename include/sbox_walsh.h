@@ -146,8 +146,9 @@ sbox_status sbox_scratch_release(void* stream);
  * Eq. 1 with y = S(x)), instead of transposing slabs (3.6 ms against
  * 6.5 ms at n = m = 16 on one MI355X).  The decision is taken again on
  * every call (and on every replay of a captured call) from the table's
- * contents at that time; a table that is not a permutation costs two
- * launches more than the slab route alone.
+ * contents at that time; a table that is not a permutation costs four
+ * short launches more than the slab route alone (the scatter, the check
+ * and the two passes of the other route, which return at once).
  */
 sbox_status sbox_walsh_nl_ex(const void* S, int n, int m, int s_elem_bytes,
                              int32_t* maxabs_per_b, int32_t* nl,
